@@ -1,0 +1,156 @@
+/*
+ * knn.h -- C ABI of libknn.so: brute-force k-NN / k-NN graph construction by
+ * GPU quick multi-select on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Komarov, Dashti & D'Souza, "Fast k-NNG construction with GPU-based
+ * quick multi-select" (arXiv:1309.5478).  The distance part is a matrix product
+ * plus norm corrections (Methods, "Distance calculation"); the selection part
+ * is the paper's two-level quick multi-select (Methods, "GPU-based quick
+ * multi-select").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every array argument is a DEVICE pointer owned by the caller (for example
+ *    the storage of a torch tensor on ROCm).  The library never frees, retains
+ *    or writes through an input pointer; inputs are const.  Outputs are written
+ *    only when the call returns KNN_SUCCESS.
+ *  - Layout is row-major.  Point sets are n x d with row stride d floats.  A
+ *    distance matrix has row stride `ld` >= cols floats.  Outputs are rows x k,
+ *    contiguous.
+ *  - Each output row is in ascending order of (value, index): the selected set
+ *    and its order are those of a stable sort of the row, so equal values
+ *    resolve to the lower column index.  FP32 values are ordered by a total
+ *    order: -0 == +0, all NaNs equal and above +inf.
+ *  - Indices are int32; any count of columns / corpus points above INT32_MAX is
+ *    rejected.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued
+ *    asynchronously on it.  Arguments are validated on the host before anything
+ *    is enqueued; on an error nothing is launched and the outputs are untouched.
+ *  - A handle owns a device workspace that grows on demand and is reused by
+ *    later calls.  Calls on one handle must be issued from one host thread at a
+ *    time and ordered on one stream (or otherwise ordered by the caller).
+ *  - Device-side faults surface as KNN_ERROR_DEVICE from the failing launch or
+ *    from knn_get_stats, which synchronises the stream.
+ */
+#ifndef KNN_H_
+#define KNN_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct knn_handle_s *knn_handle_t;
+
+typedef enum {
+    KNN_SUCCESS = 0,
+    KNN_ERROR_INVALID_VALUE = 1, /* bad pointer, size, k, stride or option      */
+    KNN_ERROR_OUT_OF_MEMORY = 2, /* workspace allocation failed                 */
+    KNN_ERROR_UNSUPPORTED = 3,   /* device is not gfx950, or a size limit is hit */
+    KNN_ERROR_DEVICE = 4,        /* a HIP runtime call or a kernel failed        */
+    KNN_ERROR_IO = 5             /* a file could not be read or written          */
+} knn_status_t;
+
+/* How the first pivot of each row is chosen.  The output never depends on it. */
+typedef enum {
+    /* lower median of a strided sample of the segment, at every pass: the
+     * paper's quickselect with the pivot rule it leaves open */
+    KNN_PIVOT_PLAIN = 0,
+    /* the sample order statistic just above the expected rank of the k-th key */
+    KNN_PIVOT_SAMPLE = 1,
+    /* the pivot network's estimate of the k-th value; rows where it is unusable
+     * fall back to KNN_PIVOT_SAMPLE */
+    KNN_PIVOT_LEARNED = 2
+} knn_pivot_t;
+
+typedef enum {
+    KNN_PREC_FP32 = 0,      /* FP32 inputs on the FP32 matrix cores             */
+    KNN_PREC_BF16 = 1,      /* BF16 (round to nearest even) inputs, FP32 accum.  */
+    KNN_PREC_FP8_E4M3 = 2   /* OCP e4m3 with a power-of-two scale per point       */
+} knn_precision_t;
+
+typedef struct {
+    int32_t pivot;      /* knn_pivot_t; default KNN_PIVOT_SAMPLE                      */
+    int32_t precision;  /* knn_precision_t; default KNN_PREC_FP32 (search / graph)    */
+    int32_t oversample; /* candidates kept before the exact re-rank = oversample * k; */
+                        /* default 4, at least 1                                      */
+    int32_t flags;      /* KNN_FLAG_* bits                                            */
+} knn_options_t;
+
+/* Force the exact-fallback path of search / graph for every row (tests). */
+#define KNN_FLAG_FORCE_FALLBACK 0x1
+/* Materialise distance tiles and select from them instead of the fused kernel. */
+#define KNN_FLAG_UNFUSED 0x2
+
+typedef struct {
+    int64_t rows;                 /* rows processed by the last call              */
+    int64_t passes_total;         /* partition passes summed over rows            */
+    int32_t passes_max;           /* most partition passes on one row             */
+    int32_t reserved0;
+    int64_t stream_passes_total;  /* full reads of an input row (select_k)        */
+    int64_t spill_rows;           /* rows whose candidates left on-chip memory    */
+    int64_t first_pass_survivors; /* keys kept by the first pass, summed          */
+    int64_t fallback_rows;        /* search / graph rows re-run on the exact path */
+    int64_t candidates_total;     /* search / graph candidates, summed            */
+} knn_stats_t;
+
+/* Create a handle bound to HIP device `device` (must be gfx950). */
+knn_status_t knn_create(knn_handle_t *out, int device);
+/* Release a handle and its workspace.  NULL is accepted. */
+knn_status_t knn_destroy(knn_handle_t h);
+/* Static description of a status code. */
+const char *knn_status_string(knn_status_t s);
+/* Detail string for the last failing call on `h` (or on no handle, if NULL). */
+const char *knn_last_error(knn_handle_t h);
+
+/*
+ * knn_select_k -- the k smallest entries of every row of a distance matrix
+ * (Introduction: brute-force selection from each row of the M x N matrix;
+ * Methods, "GPU-based quick multi-select": two-level quickselect, one workgroup
+ * per row, ballot-based partition, K-versus-L recursion with a stack of segment
+ * references).
+ *
+ *   dist     rows x cols FP32, row stride ld (>= cols)            [in, device]
+ *   k        1 <= k <= min(cols, 1024)
+ *   out_val  rows x k FP32: the selected entries, bit-for-bit copies [out]
+ *   out_idx  rows x k int32: their column indices                  [out]
+ *   opt      NULL for defaults; only `pivot` is used
+ * Errors: INVALID_VALUE for null pointers, rows < 0, cols < 1, ld < cols,
+ * k < 1 or k > cols; UNSUPPORTED for k > 1024 or cols > INT32_MAX.
+ */
+knn_status_t knn_select_k(knn_handle_t h, const float *dist, int64_t rows, int64_t cols,
+                          int64_t ld, int32_t k, float *out_val, int32_t *out_idx,
+                          void *stream, const knn_options_t *opt);
+
+/*
+ * knn_partition -- one partition pass per row, as the paper describes it for one
+ * warp per row (Methods, "GPU-based quick multi-select", and Figures 1-3): the
+ * row is read in 64-element segments, a wavefront ballot on "key below pivot"
+ * gives every lane its slot through a population count of the lanes below it,
+ * keys below the pivot are written from the left end of the output row in input
+ * order and the others from the right end (so they appear in reverse input
+ * order).  Keys are (value, column index) under the total order above.
+ *
+ *   in        rows x cols FP32, row stride ld                       [in, device]
+ *   piv_val   rows FP32 pivot values                                [in, device]
+ *   piv_idx   rows int32 pivot column indices (ties of value: a key is below
+ *             the pivot when its index is lower)                     [in, device]
+ *   out_val   rows x cols FP32 partitioned values                    [out]
+ *   out_idx   rows x cols int32 their column indices                 [out]
+ *   out_left  rows int32: L, the number of keys below the pivot      [out]
+ * Errors: INVALID_VALUE for null pointers, rows < 0, cols < 1, ld < cols.
+ */
+knn_status_t knn_partition(knn_handle_t h, const float *in, int64_t rows, int64_t cols,
+                           int64_t ld, const float *piv_val, const int32_t *piv_idx,
+                           float *out_val, int32_t *out_idx, int32_t *out_left, void *stream);
+
+/* Counters of the last select / search / graph call on `h`.  Synchronises the
+ * stream that call used. */
+knn_status_t knn_get_stats(knn_handle_t h, knn_stats_t *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KNN_H_ */

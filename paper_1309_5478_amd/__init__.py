@@ -1,0 +1,151 @@
+"""MI355X-native brute-force k-NN / k-NN graph by GPU quick multi-select.
+
+A thin binding over libknn.so (include/knn.h): every step of the computation
+runs in the library's HIP kernels; this module only checks tensors, allocates
+outputs with torch on the same device and passes device pointers and the
+current HIP stream.  Method: Komarov, Dashti & D'Souza, arXiv:1309.5478.
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _abi
+from ._abi import (PIVOT_LEARNED, PIVOT_PLAIN, PIVOT_SAMPLE, PREC_BF16, PREC_FP32,  # noqa: F401
+                   PREC_FP8_E4M3, FLAG_FORCE_FALLBACK, FLAG_UNFUSED, Options, Stats)
+
+_PIVOTS = {"plain": PIVOT_PLAIN, "sample": PIVOT_SAMPLE, "learned": PIVOT_LEARNED}
+_PRECS = {"fp32": PREC_FP32, "bf16": PREC_BF16, "fp8": PREC_FP8_E4M3}
+
+
+class KnnError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Handle:
+    """Owns a libknn handle (device workspace, statistics) on one device."""
+
+    def __init__(self, device: int = 0):
+        self.lib = _abi.load()
+        h = ctypes.c_void_p()
+        st = self.lib.knn_create(ctypes.byref(h), device)
+        if st != 0:
+            raise KnnError(st, self.lib.knn_last_error(None).decode())
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.knn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != 0:
+            raise KnnError(st, self.lib.knn_last_error(self.h).decode())
+
+    def _stream(self):
+        torch = _torch()
+        return ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    @staticmethod
+    def _opts(pivot="sample", precision="fp32", oversample=4, flags=0):
+        o = Options()
+        o.pivot = _PIVOTS[pivot] if isinstance(pivot, str) else int(pivot)
+        o.precision = _PRECS[precision] if isinstance(precision, str) else int(precision)
+        o.oversample = int(oversample)
+        o.flags = int(flags)
+        return o
+
+    def stats(self) -> dict:
+        s = Stats()
+        self._check(self.lib.knn_get_stats(self.h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def select_k(self, dist, k: int, pivot="sample"):
+        """k smallest entries per row of a 2-D FP32 CUDA tensor (row stride may
+        exceed the width).  Returns (values [rows, k] f32, indices [rows, k] i32)."""
+        torch = _torch()
+        if dist.dim() != 2 or dist.dtype != torch.float32 or not dist.is_cuda or dist.stride(1) != 1:
+            raise ValueError("dist must be a 2-D float32 device tensor with unit column stride")
+        rows, cols = dist.shape
+        vals = torch.empty((rows, k), dtype=torch.float32, device=dist.device)
+        idx = torch.empty((rows, k), dtype=torch.int32, device=dist.device)
+        o = self._opts(pivot)
+        self._check(self.lib.knn_select_k(self.h, ctypes.c_void_p(dist.data_ptr()), rows, cols,
+                                          max(dist.stride(0), cols), k, ctypes.c_void_p(vals.data_ptr()),
+                                          ctypes.c_void_p(idx.data_ptr()), self._stream(), ctypes.byref(o)))
+        return vals, idx
+
+    def partition(self, x, piv_val, piv_idx):
+        """One partition pass per row (one wave per row).  Returns (values, indices, L)."""
+        torch = _torch()
+        if x.dim() != 2 or x.dtype != torch.float32 or not x.is_cuda or x.stride(1) != 1:
+            raise ValueError("x must be a 2-D float32 device tensor with unit column stride")
+        rows, cols = x.shape
+        pv = piv_val.to(device=x.device, dtype=torch.float32).contiguous()
+        pi = piv_idx.to(device=x.device, dtype=torch.int32).contiguous()
+        ov = torch.empty((rows, cols), dtype=torch.float32, device=x.device)
+        oi = torch.empty((rows, cols), dtype=torch.int32, device=x.device)
+        L = torch.empty((rows,), dtype=torch.int32, device=x.device)
+        self._check(self.lib.knn_partition(self.h, ctypes.c_void_p(x.data_ptr()), rows, cols,
+                                           max(x.stride(0), cols), ctypes.c_void_p(pv.data_ptr()),
+                                           ctypes.c_void_p(pi.data_ptr()), ctypes.c_void_p(ov.data_ptr()),
+                                           ctypes.c_void_p(oi.data_ptr()), ctypes.c_void_p(L.data_ptr()),
+                                           self._stream()))
+        return ov, oi, L
+
+    def search(self, queries, corpus, k: int, pivot="sample", precision="fp32", oversample=4, flags=0):
+        """k nearest corpus rows per query row (squared Euclidean).
+        Returns (dist [m, k] f32, idx [m, k] i32)."""
+        torch = _torch()
+        for t in (queries, corpus):
+            if t.dim() != 2 or t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+                raise ValueError("queries and corpus must be contiguous 2-D float32 device tensors")
+        m, d = queries.shape
+        n, d2 = corpus.shape
+        if d != d2:
+            raise ValueError("queries and corpus differ in dimension")
+        dist = torch.empty((m, k), dtype=torch.float32, device=queries.device)
+        idx = torch.empty((m, k), dtype=torch.int32, device=queries.device)
+        o = self._opts(pivot, precision, oversample, flags)
+        self._check(self.lib.knn_search(self.h, ctypes.c_void_p(queries.data_ptr()), m,
+                                        ctypes.c_void_p(corpus.data_ptr()), n, d, k,
+                                        ctypes.c_void_p(dist.data_ptr()), ctypes.c_void_p(idx.data_ptr()),
+                                        self._stream(), ctypes.byref(o)))
+        return dist, idx
+
+    def graph(self, points, k: int, pivot="sample", precision="fp32", oversample=4, flags=0):
+        """k-NN graph of the rows of `points` (own index excluded).
+        Returns (dist [n, k] f32, idx [n, k] i32)."""
+        torch = _torch()
+        if points.dim() != 2 or points.dtype != torch.float32 or not points.is_cuda or not points.is_contiguous():
+            raise ValueError("points must be a contiguous 2-D float32 device tensor")
+        n, d = points.shape
+        dist = torch.empty((n, k), dtype=torch.float32, device=points.device)
+        idx = torch.empty((n, k), dtype=torch.int32, device=points.device)
+        o = self._opts(pivot, precision, oversample, flags)
+        self._check(self.lib.knn_graph(self.h, ctypes.c_void_p(points.data_ptr()), n, d, k,
+                                       ctypes.c_void_p(dist.data_ptr()), ctypes.c_void_p(idx.data_ptr()),
+                                       self._stream(), ctypes.byref(o)))
+        return dist, idx
+
+
+_default = {}
+
+
+def handle(device: int = 0) -> Handle:
+    if device not in _default:
+        _default[device] = Handle(device)
+    return _default[device]

@@ -1,0 +1,58 @@
+// Host-side declarations shared between the C ABI layer and the kernel files.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace knn {
+
+enum PivotMode : int { kPivotPlain = 0, kPivotSample = 1, kPivotLearned = 2 };
+
+// Device counters filled by the kernels of one call (uint64 each).
+enum StatSlot : int {
+    kStatRows = 0,
+    kStatPasses = 1,
+    kStatPassesMax = 2,
+    kStatStreamPasses = 3,
+    kStatSpillRows = 4,
+    kStatFirstSurvivors = 5,
+    kStatFallbackRows = 6,
+    kStatCandidates = 7,
+    kStatErrors = 8,
+    kStatCount = 9
+};
+
+// ---- selection over a given FP32 matrix ------------------------------------
+struct SelectArgs {
+    const float *dist;     // rows x cols, row stride ld
+    int64_t rows;
+    uint32_t cols;
+    int64_t ld;
+    uint32_t k;
+    float *out_val;        // rows x k
+    int32_t *out_idx;      // rows x k
+    const float *pivot_hint;  // per-row first-pivot values (learned mode) or null
+    int mode;              // PivotMode
+    unsigned long long *stats;  // kStatCount counters, or null
+};
+
+// Largest k a selection call supports.
+constexpr int kSelectMaxK = 1024;
+
+// Capacity class (keys held on chip per buffer) used for a given k.
+int select_cap_for_k(uint32_t k);
+// Workgroups to launch for `rows` rows (persistent grid) on a device with `num_cu` CUs.
+int select_grid(int cap, int64_t rows, int num_cu);
+// Global workspace bytes for a launch with `grid` workgroups over rows of `cols`.
+size_t select_ws_bytes(int cap, uint32_t cols, int grid);
+// Launch; `ws` must hold select_ws_bytes(...) bytes.
+hipError_t launch_select(const SelectArgs &a, int cap, int grid, void *ws, hipStream_t stream);
+
+// ---- one partition pass, one wavefront per row ------------------------------
+hipError_t launch_partition(const float *in, int64_t rows, uint32_t cols, int64_t ld,
+                            const float *piv_val, const int32_t *piv_idx, float *out_val,
+                            int32_t *out_idx, int32_t *out_left, hipStream_t stream);
+
+// ---- utilities ------------------------------------------------------------------
+hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t stream);
+
+}  // namespace knn

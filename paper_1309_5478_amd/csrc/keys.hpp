@@ -1,0 +1,134 @@
+// Device helpers shared by the HIP kernels of libknn: ordered keys, wavefront
+// vote helpers, in-register and LDS bitonic sorts.  gfx950, wave64.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace knn {
+
+constexpr int kWave = 64;
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr uint64_t kKeyMax = ~0ull;       // above every real key (indices are < 2^31)
+constexpr uint32_t kOrdNaN = 0xFFFFFFFFu;  // every NaN maps here
+constexpr uint32_t kOrdZero = 0x80000000u; // -0 and +0 map here
+
+// Order-preserving map of an FP32 value to uint32 under the total order used by
+// selection: -0 == +0, NaN == NaN above +inf, otherwise IEEE order.
+__device__ __forceinline__ uint32_t ord32(float v) {
+    uint32_t u = __float_as_uint(v);
+    u = (v == 0.0f) ? 0u : u;
+    uint32_t o = u ^ ((uint32_t)((int32_t)u >> 31) | 0x80000000u);
+    return (v != v) ? kOrdNaN : o;
+}
+
+// Inverse of ord32 for every class that has one representative (not for the
+// zero class, which returns +0, nor the NaN class).
+__device__ __forceinline__ float ord_to_float(uint32_t o) {
+    uint32_t u = (o & 0x80000000u) ? (o ^ 0x80000000u) : ~o;
+    return __uint_as_float(u);
+}
+
+// A selection key: value class in the high word, column index in the low word,
+// so keys are distinct and ties resolve to the lower index.
+__device__ __forceinline__ uint64_t make_key(float v, uint32_t idx) {
+    return ((uint64_t)ord32(v) << 32) | idx;
+}
+__device__ __forceinline__ uint32_t key_idx(uint64_t k) { return (uint32_t)k; }
+__device__ __forceinline__ uint32_t key_ord(uint64_t k) { return (uint32_t)(k >> 32); }
+
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & (kWave - 1); }
+
+// Number of set bits of `m` in lanes below this lane.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ uint32_t wave_bcast0(uint32_t v) {
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+// A pivot key prepared for fast comparison against (value, index) pairs.
+struct Pivot {
+    float pv;       // representative value of the pivot's class (+0 for zeros)
+    uint32_t pidx;  // pivot index
+    uint32_t nan;   // pivot is in the NaN class
+    uint32_t inf;   // pivot is the +infinity sentinel (every key is below)
+};
+
+__device__ __forceinline__ Pivot make_pivot(uint64_t key) {
+    Pivot p;
+    uint32_t o = key_ord(key);
+    p.inf = (key == kKeyMax) ? 1u : 0u;
+    p.nan = (o == kOrdNaN) ? 1u : 0u;
+    p.pv = (o == kOrdZero) ? 0.0f : ord_to_float(o);
+    p.pidx = key_idx(key);
+    return p;
+}
+
+// (v, j) < pivot in the key order.
+__device__ __forceinline__ bool key_below(float v, uint32_t j, const Pivot &p) {
+    if (p.inf) return true;
+    bool lt = p.nan ? (v == v) : (v < p.pv);
+    bool eq = p.nan ? (v != v) : (v == p.pv);
+    return lt || (eq && j < p.pidx);
+}
+
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int mask) {
+    uint32_t lo = __shfl_xor((unsigned int)(uint32_t)v, mask);
+    uint32_t hi = __shfl_xor((unsigned int)(uint32_t)(v >> 32), mask);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Ascending bitonic sort of one key per lane across the 64 lanes of a wave.
+__device__ __forceinline__ uint64_t wave_sort64(uint64_t key) {
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int size = 2; size <= kWave; size <<= 1) {
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            uint64_t other = shfl_xor_u64(key, stride);
+            bool up = (lane & size) == 0;
+            bool lower = (lane & stride) == 0;
+            bool take_min = (lower == up);
+            uint64_t mn = key < other ? key : other;
+            uint64_t mx = key < other ? other : key;
+            key = take_min ? mn : mx;
+        }
+    }
+    return key;
+}
+
+__device__ __forceinline__ uint64_t wave_readlane_u64(uint64_t v, int lane) {
+    uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, lane);
+    uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Ascending bitonic sort of n (a power of two) keys in LDS by the whole block.
+template <int NT>
+__device__ __forceinline__ void block_bitonic_sort(uint64_t *buf, uint32_t n) {
+    for (uint32_t size = 2; size <= n; size <<= 1) {
+        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+            for (uint32_t i = threadIdx.x; i < (n >> 1); i += NT) {
+                uint32_t lo = 2 * i - (i & (stride - 1));
+                uint32_t hi = lo + stride;
+                bool up = (lo & size) == 0;
+                uint64_t a = buf[lo], b = buf[hi];
+                if ((a > b) == up) {
+                    buf[lo] = b;
+                    buf[hi] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__device__ __forceinline__ uint32_t next_pow2(uint32_t x) {
+    uint32_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+}  // namespace knn

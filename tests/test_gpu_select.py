@@ -1,0 +1,204 @@
+"""Parity of the HIP selection path (knn_select_k, knn_partition) with the CPU
+oracle: bit-exact indices and value bits."""
+import ctypes
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+PIVOTS = ("plain", "sample", "learned")
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+@pytest.fixture(scope="module")
+def h(torch):
+    import paper_1309_5478_amd as knn
+    return knn.Handle(0)
+
+
+def bits(a):
+    return np.ascontiguousarray(a, dtype=np.float32).view(np.uint32)
+
+
+def check_select(h, torch, D, k, pivot, rows=None, ld_pad=0, offset=0, tag=""):
+    """Runs knn_select_k on D (optionally with padded rows / a misaligned base)
+    and compares with the oracle on every (or the listed) row."""
+    say(f"select_k {tag} shape={D.shape} k={k} pivot={pivot} ld_pad={ld_pad} offset={offset}")
+    R, C = D.shape
+    host = np.zeros(offset + R * (C + ld_pad), np.float32)
+    view = host[offset:offset + R * (C + ld_pad)].reshape(R, C + ld_pad)
+    view[:, :C] = D
+    dev = torch.from_numpy(host).cuda()
+    dmat = dev[offset:offset + R * (C + ld_pad)].view(R, C + ld_pad)[:, :C]
+    vals, idx = h.select_k(dmat, k, pivot=pivot)
+    torch.cuda.synchronize()
+    gv, gi = vals.cpu().numpy(), idx.cpu().numpy()
+    ov, oi = oracle.select_k(D, k, rows=rows)
+    if rows is not None:
+        gv, gi = gv[rows], gi[rows]
+    bad = np.nonzero((gi != oi).any(axis=1) | (bits(gv) != bits(ov)).any(axis=1))[0]
+    assert bad.size == 0, f"{bad.size} rows differ, first {bad[:5]}"
+    st = h.stats()
+    assert st["rows"] == R
+    return st
+
+
+@pytest.mark.parametrize("cols", [1, 5, 63, 64, 65, 1000, 1024, 1025, 2049, 4097, 10007, 65543])
+@pytest.mark.parametrize("pivot", PIVOTS)
+def test_select_random_sizes(h, torch, cols, pivot):
+    rng = np.random.default_rng(cols)
+    D = rng.standard_normal((37, cols)).astype(np.float32)
+    for k in sorted({1, 7, 32, 64, 65, 256, 1000, 1024, cols} & set(range(1, min(cols, 1024) + 1))):
+        check_select(h, torch, D, k, pivot, tag="random")
+
+
+@pytest.mark.parametrize("cols", [3000, 70001])
+@pytest.mark.parametrize("pivot", PIVOTS)
+def test_select_adversarial_rows(h, torch, cols, pivot):
+    adv = synth.adversarial_rows(cols, seed=12)
+    names = sorted(adv)
+    D = np.stack([adv[n] for n in names])
+    for k in (1, 32, 333, 1024):
+        check_select(h, torch, D, k, pivot, tag="adversarial:" + ",".join(names))
+
+
+@pytest.mark.parametrize("pivot", PIVOTS)
+def test_select_heavy_ties_and_layout(h, torch, pivot):
+    rng = np.random.default_rng(5)
+    D = rng.integers(0, 3, size=(20, 9000)).astype(np.float32)   # thousands of equal values
+    D[3] = 1.0
+    D[4, ::2] = -0.0
+    for k in (1, 100, 1024):
+        check_select(h, torch, D, k, pivot, tag="ties")
+        check_select(h, torch, D, k, pivot, ld_pad=3, tag="ld+3")
+        check_select(h, torch, D, k, pivot, ld_pad=0, offset=1, tag="misaligned")
+
+
+def test_select_pivot_independence_and_repeat(h, torch):
+    D = synth.sqdist_matrix_normal(300, 20000, 64, seed=2)
+    dev = torch.from_numpy(D).cuda()
+    outs = []
+    for pivot in PIVOTS * 2:
+        v, i = h.select_k(dev, 256, pivot=pivot)
+        outs.append((bits(v.cpu().numpy()).copy(), i.cpu().numpy().copy()))
+    for v, i in outs[1:]:
+        assert np.array_equal(v, outs[0][0]) and np.array_equal(i, outs[0][1])
+
+
+def test_select_empty_rows_is_noop(h, torch):
+    D = torch.zeros((0, 100), device="cuda")
+    v, i = h.select_k(D, 5)
+    assert v.shape == (0, 5)
+
+
+def test_select_argument_errors_leave_outputs(h, torch):
+    import paper_1309_5478_amd as knn
+    lib = h.lib
+    D = torch.ones((4, 16), device="cuda")
+    out_v = torch.full((4, 8), 7.0, device="cuda")
+    out_i = torch.full((4, 8), 7, dtype=torch.int32, device="cuda")
+    p = lambda t: ctypes.c_void_p(t.data_ptr())
+    cases = [
+        (dict(rows=-1), knn._abi.KNN_ERROR_INVALID_VALUE),
+        (dict(cols=0), knn._abi.KNN_ERROR_INVALID_VALUE),
+        (dict(ld=15), knn._abi.KNN_ERROR_INVALID_VALUE),
+        (dict(k=0), knn._abi.KNN_ERROR_INVALID_VALUE),
+        (dict(k=17), knn._abi.KNN_ERROR_INVALID_VALUE),
+        (dict(dist=None), knn._abi.KNN_ERROR_INVALID_VALUE),
+        (dict(cols=2000, ld=2000, k=1025), knn._abi.KNN_ERROR_UNSUPPORTED),
+        (dict(cols=1 << 31, ld=1 << 31), knn._abi.KNN_ERROR_UNSUPPORTED),
+    ]
+    for over, want in cases:
+        a = dict(dist=p(D), rows=4, cols=16, ld=16, k=8)
+        a.update(over)
+        st = lib.knn_select_k(h.h, a["dist"], a["rows"], a["cols"], a["ld"], a["k"], p(out_v), p(out_i), None, None)
+        assert st == want, (over, st, lib.knn_last_error(h.h))
+    torch.cuda.synchronize()
+    assert bool((out_v == 7.0).all()) and bool((out_i == 7).all())
+
+
+@pytest.mark.parametrize("cols", [1, 4, 63, 64, 65, 200, 4099])
+def test_partition_matches_oracle(h, torch, cols):
+    rng = np.random.default_rng(cols)
+    R = 9
+    X = rng.integers(0, 7, size=(R, cols)).astype(np.float32)
+    X[0, ::3] = np.nan
+    X[1, ::2] = -0.0
+    pj = rng.integers(0, cols, size=R).astype(np.int32)
+    pv = X[np.arange(R), pj].copy()
+    pv[2] = np.nan                    # pivot in the NaN class
+    pv[3] = 3.5                       # a value between the classes
+    say(f"partition cols={cols}")
+    ov, oi, L = h.partition(torch.from_numpy(X).cuda(), torch.from_numpy(pv), torch.from_numpy(pj))
+    ov, oi, L = ov.cpu().numpy(), oi.cpu().numpy(), L.cpu().numpy()
+    for r in range(R):
+        ev, ei, eL = oracle.partition(X[r], np.arange(cols, dtype=np.int32), float(pv[r]), int(pj[r]))
+        assert L[r] == eL
+        assert np.array_equal(oi[r], ei)
+        assert np.array_equal(bits(ov[r]), bits(ev))
+
+
+def test_partition_golden_example(h, torch):
+    from golden_io import partition_cases
+    for vals, piv, lanes, L in partition_cases():
+        x = torch.tensor([vals], dtype=torch.float32, device="cuda")
+        ov, oi, got_L = h.partition(x, torch.tensor([piv]), torch.tensor([1 << 30], dtype=torch.int32))
+        assert int(got_L[0]) == L
+        assert oi[0].cpu().tolist() == lanes
+
+
+@pytest.mark.parametrize("k", [32, 256, 1024])
+def test_select_full_size_sampled_rows(h, torch, k):
+    """16384 x 65536 squared distances of N(0,1) points in d=256: sampled rows
+    against the oracle, invariants on every row."""
+    M, N, d = 16384, 65536, 256
+    D = _full_matrix(M, N, d)
+    dev = _full_matrix_dev(torch, D)
+    rows = np.random.default_rng(k).choice(M, 48, replace=False)
+    say(f"select_k full size k={k}")
+    for pivot in ("sample", "plain"):
+        v, i = h.select_k(dev, k, pivot=pivot)
+        torch.cuda.synchronize()
+        gv, gi = v.cpu().numpy(), i.cpu().numpy()
+        st = h.stats()
+        say(f"  pivot={pivot} stats={st}")
+        ov, oi = oracle.select_k(D, k, rows=rows)
+        assert np.array_equal(gi[rows], oi)
+        assert np.array_equal(bits(gv[rows]), bits(ov))
+        # every row: indices in range and distinct, values copied, ascending
+        assert gi.min() >= 0 and gi.max() < N
+        srt = np.sort(gi, axis=1)
+        assert not (srt[:, 1:] == srt[:, :-1]).any()
+        assert np.array_equal(bits(np.take_along_axis(D, gi.astype(np.int64), axis=1)), bits(gv))
+        assert (np.diff(gv, axis=1) >= 0).all()
+
+
+_CACHE = {}
+
+
+def _full_matrix(M, N, d):
+    if "D" not in _CACHE:
+        say("generating the 16384 x 65536 select matrix")
+        _CACHE["D"] = synth.sqdist_matrix_normal(M, N, d, seed=synth.SEEDS["select"])
+    return _CACHE["D"]
+
+
+def _full_matrix_dev(torch, D):
+    if "dev" not in _CACHE:
+        _CACHE["dev"] = torch.from_numpy(D).cuda()
+    return _CACHE["dev"]
