@@ -93,6 +93,8 @@ typedef struct {
     int64_t first_pass_survivors; /* keys kept by the first pass, summed          */
     int64_t fallback_rows;        /* search / graph rows re-run on the exact path */
     int64_t candidates_total;     /* search / graph candidates, summed            */
+    int64_t phase_cycles[4];      /* shader clocks summed over rows: first pivot, */
+                                  /* streaming passes, on-chip passes, final sort */
 } knn_stats_t;
 
 /* Create a handle bound to HIP device `device` (must be gfx950). */

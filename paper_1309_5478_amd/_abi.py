@@ -29,10 +29,13 @@ class Stats(ctypes.Structure):
                 ("passes_max", ctypes.c_int32), ("reserved0", ctypes.c_int32),
                 ("stream_passes_total", ctypes.c_int64), ("spill_rows", ctypes.c_int64),
                 ("first_pass_survivors", ctypes.c_int64), ("fallback_rows", ctypes.c_int64),
-                ("candidates_total", ctypes.c_int64)]
+                ("candidates_total", ctypes.c_int64), ("phase_cycles", ctypes.c_int64 * 4)]
 
     def as_dict(self):
-        return {name: int(getattr(self, name)) for name, _ in self._fields_ if name != "reserved0"}
+        d = {name: int(getattr(self, name)) for name, _ in self._fields_
+             if name not in ("reserved0", "phase_cycles")}
+        d["phase_cycles"] = [int(x) for x in self.phase_cycles]
+        return d
 
 
 _P = ctypes.c_void_p

@@ -207,6 +207,10 @@ knn_status_t knn_get_stats(knn_handle_t h, knn_stats_t *out) {
         t.first_pass_survivors = (int64_t)s[kStatFirstSurvivors];
         t.fallback_rows = (int64_t)s[kStatFallbackRows];
         t.candidates_total = (int64_t)s[kStatCandidates];
+        t.phase_cycles[0] = (int64_t)s[kStatCycSample];
+        t.phase_cycles[1] = (int64_t)s[kStatCycStream];
+        t.phase_cycles[2] = (int64_t)s[kStatCycSelect];
+        t.phase_cycles[3] = (int64_t)s[kStatCycFinal];
         h->last = t;
         h->stats_pending = false;
     }

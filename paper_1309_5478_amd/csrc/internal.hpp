@@ -18,7 +18,11 @@ enum StatSlot : int {
     kStatFallbackRows = 6,
     kStatCandidates = 7,
     kStatErrors = 8,
-    kStatCount = 9
+    kStatCycSample = 9,
+    kStatCycStream = 10,
+    kStatCycSelect = 11,
+    kStatCycFinal = 12,
+    kStatCount = 13
 };
 
 // ---- selection over a given FP32 matrix ------------------------------------

@@ -54,95 +54,142 @@ struct SelSmem {
     uint32_t cnt_ge;
 };
 
-template <int CAP>
-struct VBuf {
-    SelSmem<CAP> &sm;
-    uint64_t *g[2];  // global parts (positions >= CAP), per buffer
-
-    __device__ __forceinline__ uint64_t ld(uint32_t b, uint32_t p) const {
-        return p < CAP ? sm.buf[b][p] : g[b][p - CAP];
-    }
-    __device__ __forceinline__ void st(uint32_t b, uint32_t p, uint64_t v) const {
-        if (p < CAP) sm.buf[b][p] = v;
-        else g[b][p - CAP] = v;
-    }
+// The two partition buffers: positions below CAP live in LDS, the rest in a
+// per-workgroup global workspace.  LDS is reached through the kernel's
+// __shared__ object passed down by reference (never stored in a struct), so
+// LDS accesses stay ds_* instructions.
+struct GBuf {
+    uint64_t *g0, *g1;
+    // select, not an indexed array: a runtime-indexed array would live in scratch
+    __device__ __forceinline__ uint64_t *at(uint32_t b) const { return b ? g1 : g0; }
 };
+
+// The global side uses relaxed workgroup-scope atomic accesses: they cannot be
+// merged with the LDS side into one flat access, and barriers order them.
+template <int CAP>
+__device__ __forceinline__ uint64_t vld(SelSmem<CAP> &sm, const GBuf &gb, uint32_t b, uint32_t p) {
+    if (p < CAP) return sm.buf[b][p];
+    return __hip_atomic_load(gb.at(b) + (p - CAP), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+template <int CAP>
+__device__ __forceinline__ void vst(SelSmem<CAP> &sm, const GBuf &gb, uint32_t b, uint32_t p, uint64_t v) {
+    if (p < CAP) sm.buf[b][p] = v;
+    else __hip_atomic_store(gb.at(b) + (p - CAP), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
 
 // Wave-level append of the lanes set in `m` into buffer 0 at the running counter.
 template <int CAP>
-__device__ __forceinline__ void wave_append(const VBuf<CAP> &vb, uint64_t m, bool mine, float v,
+__device__ __forceinline__ void wave_append(SelSmem<CAP> &sm, const GBuf &gb, uint64_t m, bool mine, float v,
                                             uint32_t j) {
     const uint32_t lane = lane_id();
     uint32_t base = 0;
-    if (lane == 0) base = atomicAdd(&vb.sm.cnt_lt, (uint32_t)__popcll(m));
+    if (lane == 0) base = atomicAdd(&sm.cnt_lt, (uint32_t)__popcll(m));
     base = wave_bcast0(base);
-    if (mine) vb.st(0, base + lanes_below(m), make_key(v, j));
+    if (mine) vst(sm, gb, 0, base + lanes_below(m), make_key(v, j));
 }
 
-// Ballot of one entry per lane against the pivot (and, in band passes, the lower
-// bound) followed by the wave append of the survivors.
+// Generic vote of one entry per lane: key in [LO, P) (BAND) or below P, then
+// the wave append of the survivors.  Used for masked tails, band passes and
+// pivots in the NaN class or at the +infinity sentinel.
 template <int CAP, bool BAND>
-__device__ __forceinline__ void vote_append(const VBuf<CAP> &vb, float v, uint32_t j, bool valid,
-                                            const Pivot &P, const Pivot &LO) {
-    if (!BAND && !P.nan && !P.inf) {
-        uint64_t m = __ballot(valid && v < P.pv);
-        uint64_t meq = __ballot(valid && v == P.pv);
-        if (meq) m |= __ballot(valid && v == P.pv && j < P.pidx);
-        if (m) wave_append(vb, m, (m >> lane_id()) & 1ull, v, j);
-    } else {
-        bool s = valid && key_below(v, j, P) && !(BAND && key_below(v, j, LO));
-        uint64_t m = __ballot(s);
-        if (m) wave_append(vb, m, s, v, j);
+__device__ __forceinline__ void vote_generic(SelSmem<CAP> &sm, const GBuf &gb, float v, uint32_t j, bool valid,
+                                             const Pivot &P, const Pivot &LO) {
+    bool s = valid & key_below(v, j, P) & !(BAND && key_below(v, j, LO));
+    uint64_t m = __ballot(s);
+    if (m) wave_append(sm, gb, m, s, v, j);
+}
+
+constexpr uint32_t kStreamU = 4;                      // 16-byte loads per lane per tile
+constexpr uint32_t kTile4 = kSelThreads * kStreamU;   // float4s per tile
+
+// Votes one full tile (4 x float4 per lane, 16 entries) against a threshold
+// value: entries with v <= tv survive (the threshold key (ord(tv), ~0u) sits
+// above every key of that value).  One compare and one ballot per entry, one LDS
+// atomic per wave for the whole tile, then each non-empty ballot writes its
+// survivors at the running offset plus the lane's mbcnt slot.
+template <int CAP>
+__device__ __forceinline__ void vote_tile_le(SelSmem<CAP> &sm, const GBuf &gb, const f32x4 *x, uint32_t t,
+                                             float tv) {
+    const uint32_t tid = threadIdx.x, lane = lane_id();
+    uint64_t m[kStreamU * 4];
+    uint32_t total = 0;
+#pragma unroll
+    for (uint32_t u = 0; u < kStreamU; ++u) {
+        m[4 * u + 0] = __ballot(x[u].x <= tv);
+        m[4 * u + 1] = __ballot(x[u].y <= tv);
+        m[4 * u + 2] = __ballot(x[u].z <= tv);
+        m[4 * u + 3] = __ballot(x[u].w <= tv);
+    }
+#pragma unroll
+    for (uint32_t i = 0; i < kStreamU * 4; ++i) total += (uint32_t)__popcll(m[i]);
+    if (total == 0) return;
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(&sm.cnt_lt, total);
+    base = wave_bcast0(base);
+#pragma unroll
+    for (uint32_t u = 0; u < kStreamU; ++u) {
+        const uint32_t j = (t * kTile4 + u * kSelThreads + tid) * 4;
+#pragma unroll
+        for (uint32_t c = 0; c < 4; ++c) {
+            const uint64_t mm = m[4 * u + c];
+            if (mm) {
+                if ((mm >> lane) & 1ull) vst(sm, gb, 0, base + lanes_below(mm), make_key(x[u][c], j + c));
+                base += (uint32_t)__popcll(mm);
+            }
+        }
     }
 }
 
-// One streaming pass over the row: appends the keys in [LO, P) to buffer 0.
-template <int CAP, bool BAND>
-__device__ void stream_pass(const VBuf<CAP> &vb, const float *__restrict__ row, uint32_t N,
-                            bool vec, const Pivot &P, const Pivot &LO) {
-    const uint32_t tid = threadIdx.x;
-    constexpr int U = 4;
-    if (vec) {
-        const uint32_t n4 = N >> 2;
-        const f32x4 *r4 = reinterpret_cast<const f32x4 *>(row);
-        for (uint32_t it = 0; it < n4; it += kSelThreads * U) {
-            f32x4 v[U];
+// Full tiles of 256 lanes x 4 x 16 bytes against a threshold value, unmasked,
+// software-pipelined over two register sets: the loads of one tile are in flight
+// while the other is voted on (no copies between the sets, so the wait counts
+// only cover the tile being voted on).
+template <int CAP>
+__device__ __forceinline__ void stream_tiles_le(SelSmem<CAP> &sm, const GBuf &gb, const f32x4 *__restrict__ r4,
+                                                uint32_t full, float tv) {
+    const f32x4 *p = r4 + threadIdx.x;
+    f32x4 A[kStreamU], B[kStreamU];
+    auto load = [&](f32x4 *dst, uint32_t t) {
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                uint32_t i4 = it + u * kSelThreads + tid;
-                v[u] = i4 < n4 ? __builtin_nontemporal_load(r4 + i4) : f32x4{0.f, 0.f, 0.f, 0.f};
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                uint32_t i4 = it + u * kSelThreads + tid;
-                bool valid = i4 < n4;
-                uint32_t j = i4 * 4;
-                vote_append<CAP, BAND>(vb, v[u].x, j + 0, valid, P, LO);
-                vote_append<CAP, BAND>(vb, v[u].y, j + 1, valid, P, LO);
-                vote_append<CAP, BAND>(vb, v[u].z, j + 2, valid, P, LO);
-                vote_append<CAP, BAND>(vb, v[u].w, j + 3, valid, P, LO);
-            }
-        }
-        for (uint32_t j0 = n4 * 4; j0 < N; j0 += kSelThreads) {
-            uint32_t j = j0 + tid;
-            bool valid = j < N;
-            float v = valid ? row[j] : 0.f;
-            vote_append<CAP, BAND>(vb, v, j, valid, P, LO);
-        }
+        for (uint32_t u = 0; u < kStreamU; ++u) dst[u] = __builtin_nontemporal_load(p + t * kTile4 + u * kSelThreads);
+    };
+    load(A, 0);
+    uint32_t t = 0;
+    for (; t + 2 < full; t += 2) {
+        load(B, t + 1);
+        vote_tile_le(sm, gb, A, t, tv);
+        load(A, t + 2);
+        vote_tile_le(sm, gb, B, t + 1, tv);
+    }
+    if (t + 1 < full) {
+        load(B, t + 1);
+        vote_tile_le(sm, gb, A, t, tv);
+        vote_tile_le(sm, gb, B, t + 1, tv);
     } else {
-        for (uint32_t j0 = 0; j0 < N; j0 += kSelThreads * U) {
-            float v[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                uint32_t j = j0 + u * kSelThreads + tid;
-                v[u] = j < N ? row[j] : 0.f;
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                uint32_t j = j0 + u * kSelThreads + tid;
-                vote_append<CAP, BAND>(vb, v[u], j, j < N, P, LO);
-            }
-        }
+        vote_tile_le(sm, gb, A, t, tv);
+    }
+}
+
+// One streaming pass over the row, appending to buffer 0 the keys in [LO, P)
+// (BAND) or below P.  A threshold-form pivot (index ~0u) of a finite value
+// class on 16-byte aligned rows takes the tiled fast path for all full tiles;
+// everything else (band passes, NaN-class pivots, the +infinity sentinel,
+// misaligned rows, the ragged tail) takes the generic one-entry-per-lane loop.
+template <int CAP, bool BAND>
+__device__ __forceinline__ void stream_pass(SelSmem<CAP> &sm, const GBuf &gb, const float *__restrict__ row,
+                                            uint32_t N, bool vec, const Pivot &P, const Pivot &LO) {
+    const uint32_t tid = threadIdx.x;
+    uint32_t done = 0;
+    if (!BAND && vec && !P.nan && !P.inf && P.pidx == 0xFFFFFFFFu) {
+        const uint32_t full = (N >> 2) / kTile4;
+        if (full > 0) stream_tiles_le(sm, gb, reinterpret_cast<const f32x4 *>(row), full, P.pv);
+        done = full * kTile4 * 4;
+    }
+    for (uint32_t j0 = done; j0 < N; j0 += kSelThreads) {
+        uint32_t j = j0 + tid;
+        bool valid = j < N;
+        float v = valid ? row[j] : 0.f;
+        vote_generic<CAP, BAND>(sm, gb, v, j, valid, P, LO);
     }
 }
 
@@ -150,44 +197,44 @@ __device__ void stream_pass(const VBuf<CAP> &vb, const float *__restrict__ row, 
 // positions): keys below P from the left end, the others from the right end.
 // Returns L, the number of keys below P.
 template <int CAP>
-__device__ uint32_t partition_pass(const VBuf<CAP> &vb, uint32_t xb, uint32_t s, uint32_t e,
+__device__ __forceinline__ uint32_t partition_pass(SelSmem<CAP> &sm, const GBuf &gb, uint32_t xb, uint32_t s, uint32_t e,
                                    uint64_t P) {
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
     const uint32_t yb = xb ^ 1u;
     if (tid == 0) {
-        vb.sm.cnt_lt = 0;
-        vb.sm.cnt_ge = 0;
+        sm.cnt_lt = 0;
+        sm.cnt_ge = 0;
     }
     __syncthreads();
     for (uint32_t p0 = s + wave * kWave; p0 < e; p0 += kSelWaves * kWave) {
         uint32_t p = p0 + lane;
         bool valid = p < e;
-        uint64_t key = valid ? vb.ld(xb, p) : kKeyMax;
+        uint64_t key = valid ? vld(sm, gb, xb, p) : kKeyMax;
         bool lt = valid && key < P;
         bool ge = valid && !lt;
         uint64_t mlt = __ballot(lt), mge = __ballot(ge);
         uint32_t bl = 0, bg = 0;
         if (lane == 0) {
-            bl = atomicAdd(&vb.sm.cnt_lt, (uint32_t)__popcll(mlt));
-            bg = atomicAdd(&vb.sm.cnt_ge, (uint32_t)__popcll(mge));
+            bl = atomicAdd(&sm.cnt_lt, (uint32_t)__popcll(mlt));
+            bg = atomicAdd(&sm.cnt_ge, (uint32_t)__popcll(mge));
         }
         bl = wave_bcast0(bl);
         bg = wave_bcast0(bg);
-        if (lt) vb.st(yb, s + bl + lanes_below(mlt), key);
-        if (ge) vb.st(yb, e - 1 - (bg + lanes_below(mge)), key);
+        if (lt) vst(sm, gb, yb, s + bl + lanes_below(mlt), key);
+        if (ge) vst(sm, gb, yb, e - 1 - (bg + lanes_below(mge)), key);
     }
     __syncthreads();
-    uint32_t L = vb.sm.cnt_lt;
+    uint32_t L = sm.cnt_lt;
     __syncthreads();
     return L;
 }
 
 // Copies the referenced kept segments into sortbuf[agg...), returns the new agg.
 template <int CAP>
-__device__ uint32_t flush_stack(const VBuf<CAP> &vb, uint32_t nstack, uint32_t agg) {
+__device__ __forceinline__ uint32_t flush_stack(SelSmem<CAP> &sm, const GBuf &gb, uint32_t nstack, uint32_t agg) {
     for (uint32_t i = 0; i < nstack; ++i) {
-        uint32_t b = vb.sm.st_b[i], s = vb.sm.st_s[i], e = vb.sm.st_e[i];
-        for (uint32_t p = s + threadIdx.x; p < e; p += kSelThreads) vb.sm.sortbuf[agg + (p - s)] = vb.ld(b, p);
+        uint32_t b = sm.st_b[i], s = sm.st_s[i], e = sm.st_e[i];
+        for (uint32_t p = s + threadIdx.x; p < e; p += kSelThreads) sm.sortbuf[agg + (p - s)] = vld(sm, gb, b, p);
         agg += e - s;
     }
     __syncthreads();
@@ -197,30 +244,96 @@ __device__ uint32_t flush_stack(const VBuf<CAP> &vb, uint32_t nstack, uint32_t a
 // Pushes a kept segment reference.  Every thread calls it with the same values
 // and tracks nstack / agg identically.
 template <int CAP>
-__device__ void push_seg(const VBuf<CAP> &vb, uint32_t b, uint32_t s, uint32_t e, uint32_t &nstack,
+__device__ __forceinline__ void push_seg(SelSmem<CAP> &sm, const GBuf &gb, uint32_t b, uint32_t s, uint32_t e, uint32_t &nstack,
                          uint32_t &agg, bool sortbuf_free) {
     if (s == e) return;
     if (nstack == kStackDepth) {
         // Only reachable after the sample is no longer needed (the stream phase
         // pushes at most a handful of segments).
         (void)sortbuf_free;
-        agg = flush_stack(vb, nstack, agg);
+        agg = flush_stack(sm, gb, nstack, agg);
         nstack = 0;
     }
     if (threadIdx.x == 0) {
-        vb.sm.st_b[nstack] = b;
-        vb.sm.st_s[nstack] = s;
-        vb.sm.st_e[nstack] = e;
+        sm.st_b[nstack] = b;
+        sm.st_s[nstack] = s;
+        sm.st_e[nstack] = e;
     }
     ++nstack;
     __syncthreads();
 }
 
-__device__ __forceinline__ uint32_t target_rank(uint32_t S, uint32_t K, uint32_t len, float z,
-                                                float add) {
+// Index into an ascending sample of S keys whose element lies just above the
+// expected position of the K-th smallest of `len` keys (z standard deviations of
+// the binomial count plus `add`).
+__device__ __forceinline__ uint32_t target_rank(uint32_t S, uint32_t K, uint32_t len, float z, float add) {
     float mu = (float)S * (float)K / (float)len;
     float r = mu + z * sqrtf(mu) + add;
     return r >= (float)(S - 1) ? S - 1 : (uint32_t)r;
+}
+
+// Pivot index into an ascending 64-key sample of a segment of `len` keys of
+// which Kp are still needed.  When Kp is in the lower half the pivot is aimed
+// just above the Kp-th key (so L >= Kp and the segment shrinks to about Kp);
+// in the upper half just below it (so L < Kp, the left side is kept and the
+// remaining segment is about len - Kp).  The index is in [1, 63], so both sides
+// are non-empty and every pass shrinks the segment.
+__device__ __forceinline__ uint32_t lds_pivot_rank(uint32_t Kp, uint32_t len) {
+    if (2 * Kp <= len) {
+        uint32_t r = target_rank(kWave, Kp, len, 2.0f, 1.0f);
+        return r < 1 ? 1 : r;
+    }
+    float mu = (float)kWave * (float)(len - Kp) / (float)len;
+    float up = mu + 2.0f * sqrtf(mu) + 1.0f;
+    int r = (kWave - 1) - (int)up;
+    return r < 1 ? 1u : (uint32_t)r;
+}
+
+// 16 strided blocks of 64 contiguous row entries into sortbuf; each block is
+// sorted in registers by its wave (four blocks per wave, loads issued first).
+template <int CAP>
+__device__ __forceinline__ void load_sample_blocks(SelSmem<CAP> &sm, const float *row, uint32_t N) {
+    const uint32_t lane = lane_id(), wave = threadIdx.x / kWave;
+    constexpr uint32_t per = kSampleBlocks / kSelWaves;
+    float v[per];
+    uint32_t j[per];
+#pragma unroll
+    for (uint32_t i = 0; i < per; ++i) {
+        uint32_t b = wave + i * kSelWaves;
+        uint32_t start = (uint32_t)(((uint64_t)b * (N - kWave)) / (kSampleBlocks - 1));
+        j[i] = start + lane;
+        v[i] = row[j[i]];
+    }
+#pragma unroll
+    for (uint32_t i = 0; i < per; ++i) {
+        uint32_t b = wave + i * kSelWaves;
+        sm.sortbuf[b * kWave + lane] = wave_sort64(make_key(v[i], j[i]));
+    }
+    __syncthreads();
+}
+
+// The r-th smallest (0-based, r < 64) key of 16 sorted blocks of 64 in sortbuf,
+// by an r-step 16-way merge in one wave.  Called by wave 0 only.
+template <int CAP>
+__device__ __forceinline__ uint64_t merge_rank(SelSmem<CAP> &sm, uint32_t r) {
+    const uint32_t lane = lane_id();
+    uint32_t pos = 0;
+    uint64_t head = lane < (uint32_t)kSampleBlocks ? sm.sortbuf[lane * kWave] : kKeyMax;
+    uint64_t mn = kKeyMax;
+    for (uint32_t step = 0; step <= r; ++step) {
+        mn = head;
+#pragma unroll
+        for (int off = 1; off < kSampleBlocks; off <<= 1) {
+            uint64_t o = shfl_xor_u64(mn, off);
+            mn = o < mn ? o : mn;
+        }
+        mn = wave_readlane_u64(mn, 0);
+        if (lane < (uint32_t)kSampleBlocks && head == mn) {
+            ++pos;
+            head = pos < (uint32_t)kWave ? sm.sortbuf[lane * kWave + pos] : kKeyMax;
+        }
+    }
+    return mn;
 }
 
 template <int CAP>
@@ -229,12 +342,13 @@ __global__ __launch_bounds__(kSelThreads) void select_rows_kernel(SelectArgs a, 
     __shared__ SelSmem<CAP> sm;
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
     const uint32_t N = a.cols, k = a.k;
-    VBuf<CAP> vb{sm, {ws + (uint64_t)blockIdx.x * 2 * ws_slot, ws + (uint64_t)blockIdx.x * 2 * ws_slot + ws_slot}};
+    GBuf gb{ws + (uint64_t)blockIdx.x * 2 * ws_slot, ws + (uint64_t)blockIdx.x * 2 * ws_slot + ws_slot};
     const bool vec = ((reinterpret_cast<uintptr_t>(a.dist) & 15u) == 0) && ((a.ld & 3) == 0);
 
     for (int64_t r = blockIdx.x; r < a.rows; r += gridDim.x) {
         const float *row = a.dist + r * a.ld;
         uint32_t nstack = 0, agg = 0, passes = 0, stream_passes = 0, spill = 0, first = 0;
+        long long cyc_sample = 0, cyc_stream = 0;
         uint32_t sb, ss, se, Kp;  // active segment (buffer, start, end) and keys still needed
 
         if (N <= (uint32_t)CAP) {
@@ -242,32 +356,56 @@ __global__ __launch_bounds__(kSelThreads) void select_rows_kernel(SelectArgs a, 
             __syncthreads();
             sb = 0; ss = 0; se = N; Kp = k;
         } else {
-            // 1. strided sample: 16 blocks of 64 contiguous entries
-            for (uint32_t b = wave; b < (uint32_t)kSampleBlocks; b += kSelWaves) {
-                uint32_t start = (uint32_t)(((uint64_t)b * (N - kWave)) / (kSampleBlocks - 1));
-                uint32_t j = start + lane;
-                sm.sortbuf[b * kWave + lane] = make_key(row[j], j);
-            }
-            __syncthreads();
-            block_bitonic_sort<kSelThreads>(sm.sortbuf, kSortN);
-
-            uint32_t rr;
+            // 1. first pivot from a strided sample of the row
+            long long t0 = clock64();
             uint64_t P;
+            bool sample_sorted = false, sample_loaded = false;
             if (a.mode == kPivotPlain) {
-                rr = (kSortN - 1) / 2;
-                P = sm.sortbuf[rr];
+                // lower median of 64 strided entries
+                if (wave == 0) {
+                    uint32_t j = (uint32_t)(((uint64_t)lane * N) >> 6);
+                    uint64_t key = wave_sort64(make_key(row[j], j));
+                    uint64_t piv = wave_readlane_u64(key, (kWave - 1) / 2);
+                    if (lane == 0) sm.pivot = piv;
+                }
+                __syncthreads();
+                P = sm.pivot;
             } else {
-                rr = target_rank(kSortN, k, N, 3.0f, 3.0f);
-                P = sm.sortbuf[rr];
+                load_sample_blocks(sm, row, N);
+                sample_loaded = true;
+                uint32_t rr0 = target_rank(kSortN, k, N, 3.0f, 3.0f);
+                if (rr0 < (uint32_t)kWave) {
+                    if (wave == 0) {
+                        uint64_t piv = merge_rank(sm, rr0);
+                        if (lane == 0) sm.pivot = piv;
+                    }
+                    __syncthreads();
+                    P = sm.pivot;
+                } else {
+                    block_bitonic_sort<kSelThreads>(sm.sortbuf, kSortN);
+                    sample_sorted = true;
+                    P = sm.sortbuf[rr0];
+                }
                 if (a.mode == kPivotLearned && a.pivot_hint) {
-                    float h = a.pivot_hint[r];
+                    float hv = a.pivot_hint[r];
                     // a usable hint is finite and above the smallest sampled key
-                    if (h == h && fabsf(h) <= 3.0e38f) {
-                        uint64_t hk = ((uint64_t)ord32(h) << 32);
-                        if (hk > sm.sortbuf[0]) P = hk;
+                    if (hv == hv && fabsf(hv) <= 3.0e38f) {
+                        uint64_t hk = ((uint64_t)ord32(hv) << 32);
+                        uint64_t smin = sm.sortbuf[0];
+                        if (!sample_sorted) {
+                            for (int b2 = 1; b2 < kSampleBlocks; ++b2) {
+                                uint64_t c = sm.sortbuf[b2 * kWave];
+                                smin = c < smin ? c : smin;
+                            }
+                        }
+                        if (hk > smin) P = hk;
                     }
                 }
             }
+            long long t1 = clock64();
+            cyc_sample += t1 - t0;
+            // threshold form: every key of the pivot's value class is below it
+            P |= 0xFFFFFFFFull;
             // 2. streaming passes until at least Kp keys are below the pivot
             uint64_t LOk = 0;
             uint32_t base = 0;
@@ -277,10 +415,10 @@ __global__ __launch_bounds__(kSelThreads) void select_rows_kernel(SelectArgs a, 
                 __syncthreads();
                 Pivot Pv = make_pivot(P);
                 if (LOk == 0) {
-                    stream_pass<CAP, false>(vb, row, N, vec, Pv, Pv);
+                    stream_pass<CAP, false>(sm, gb, row, N, vec, Pv, Pv);
                 } else {
                     Pivot Lv = make_pivot(LOk);
-                    stream_pass<CAP, true>(vb, row, N, vec, Pv, Lv);
+                    stream_pass<CAP, true>(sm, gb, row, N, vec, Pv, Lv);
                 }
                 __syncthreads();
                 uint32_t total = sm.cnt_lt;
@@ -294,24 +432,43 @@ __global__ __launch_bounds__(kSelThreads) void select_rows_kernel(SelectArgs a, 
                     break;
                 }
                 // too few below the pivot: keep them all, move the band up
-                push_seg(vb, 0, base, total, nstack, agg, false);
+                push_seg(sm, gb, 0, base, total, nstack, agg, false);
                 Kp -= L;
                 base = total;
                 LOk = P;
-                if (P == kKeyMax) break;  // unreachable: all keys are below the sentinel
-                // next pivot: a sample key well above the old one, else the sentinel
-                rr = rr * 2 + 8 < (uint32_t)kSortN - 1 ? rr * 2 + 8 : (uint32_t)kSortN - 1;
-                while (rr < (uint32_t)kSortN - 1 && sm.sortbuf[rr] <= LOk) ++rr;
-                P = sm.sortbuf[rr] > LOk ? sm.sortbuf[rr] : kKeyMax;
+                if (P == kKeyMax) break;  // unreachable: every key is below the sentinel
+                if (!sample_loaded) {
+                    load_sample_blocks(sm, row, N);
+                    sample_loaded = true;
+                }
+                if (!sample_sorted) {
+                    block_bitonic_sort<kSelThreads>(sm.sortbuf, kSortN);
+                    sample_sorted = true;
+                }
+                // next pivot: about twice as far into the sample as the old one
+                uint32_t lo = 0, hi = kSortN;  // first sample key above LOk
+                while (lo < hi) {
+                    uint32_t mid = (lo + hi) / 2;
+                    if (sm.sortbuf[mid] <= LOk) lo = mid + 1;
+                    else hi = mid;
+                }
+                if (lo >= (uint32_t)kSortN) {
+                    P = kKeyMax;
+                } else {
+                    uint32_t rr = 2 * lo + 8 < (uint32_t)kSortN - 1 ? 2 * lo + 8 : (uint32_t)kSortN - 1;
+                    P = sm.sortbuf[rr] | 0xFFFFFFFFull;
+                }
             }
+            cyc_stream += clock64() - t1;
         }
 
         // 3. quickselect passes over the active segment
+        long long t2 = clock64();
         uint32_t nfinal = 0;
         for (;;) {
             uint32_t len = se - ss;
             if (Kp == len) {
-                push_seg(vb, sb, ss, se, nstack, agg, true);
+                push_seg(sm, gb, sb, ss, se, nstack, agg, true);
                 break;
             }
             if (passes >= (uint32_t)kMaxPasses) {
@@ -323,7 +480,7 @@ __global__ __launch_bounds__(kSelThreads) void select_rows_kernel(SelectArgs a, 
             if (len <= (uint32_t)kWave) {
                 // finish: sort the (at most 64) remaining keys in one wave
                 if (wave == 0) {
-                    uint64_t key = lane < len ? vb.ld(sb, ss + lane) : kKeyMax;
+                    uint64_t key = lane < len ? vld(sm, gb, sb, ss + lane) : kKeyMax;
                     key = wave_sort64(key);
                     if (lane < Kp) sm.finals[lane] = key;
                 }
@@ -333,38 +490,35 @@ __global__ __launch_bounds__(kSelThreads) void select_rows_kernel(SelectArgs a, 
             }
             if (wave == 0) {
                 uint32_t p = ss + (uint32_t)(((uint64_t)lane * len) >> 6);
-                uint64_t key = wave_sort64(vb.ld(sb, p));
-                uint32_t rk = (a.mode == kPivotPlain) ? 31u : target_rank(kWave, Kp, len, 2.0f, 1.0f);
+                uint64_t key = wave_sort64(vld(sm, gb, sb, p));
+                uint32_t rk = (a.mode == kPivotPlain) ? (uint32_t)(kWave - 1) / 2 : lds_pivot_rank(Kp, len);
                 uint64_t piv = wave_readlane_u64(key, rk);
                 if (lane == 0) sm.pivot = piv;
             }
             __syncthreads();
             uint64_t P = sm.pivot;
-            uint32_t L = partition_pass(vb, sb, ss, se, P);
+            uint32_t L = partition_pass(sm, gb, sb, ss, se, P);
             ++passes;
             uint32_t yb = sb ^ 1u;
             if (Kp < L) {
                 sb = yb; se = ss + L;
             } else if (Kp > L) {
-                push_seg(vb, yb, ss, ss + L, nstack, agg, true);
+                push_seg(sm, gb, yb, ss, ss + L, nstack, agg, true);
                 sb = yb; ss = ss + L; Kp -= L;
             } else {
-                push_seg(vb, yb, ss, ss + L, nstack, agg, true);
+                push_seg(sm, gb, yb, ss, ss + L, nstack, agg, true);
                 break;
             }
         }
 
         // 4. gather kept keys, sort, write out
-        agg = flush_stack(vb, nstack, agg);
+        long long t3 = clock64();
+        agg = flush_stack(sm, gb, nstack, agg);
         for (uint32_t t = tid; t < nfinal; t += kSelThreads) sm.sortbuf[agg + t] = sm.finals[t];
         agg += nfinal;
-        const uint32_t kp2 = next_pow2(k);
-        // (agg == k on every normal exit)
-        for (uint32_t t = agg + tid; t < kp2; t += kSelThreads) sm.sortbuf[t] = kKeyMax;
         __syncthreads();
-        block_bitonic_sort<kSelThreads>(sm.sortbuf, kp2);
-        for (uint32_t t = tid; t < k; t += kSelThreads) {
-            uint64_t key = sm.sortbuf[t];
+        // (agg == k on every normal exit)
+        auto emit = [&](uint32_t t, uint64_t key) {
             uint32_t idx = key_idx(key), o = key_ord(key);
             float v;
             if (key == kKeyMax) {  // only on the reported internal-error path
@@ -375,7 +529,20 @@ __global__ __launch_bounds__(kSelThreads) void select_rows_kernel(SelectArgs a, 
             }
             a.out_val[r * k + t] = v;
             a.out_idx[r * k + t] = (int32_t)idx;
+        };
+        if (k <= (uint32_t)kWave) {
+            if (wave == 0) {
+                uint64_t key = wave_sort64(lane < agg ? sm.sortbuf[lane] : kKeyMax);
+                if (lane < k) emit(lane, key);
+            }
+        } else {
+            const uint32_t kp2 = next_pow2(k);
+            for (uint32_t t = agg + tid; t < kp2; t += kSelThreads) sm.sortbuf[t] = kKeyMax;
+            __syncthreads();
+            block_bitonic_sort<kSelThreads>(sm.sortbuf, kp2);
+            for (uint32_t t = tid; t < k; t += kSelThreads) emit(t, sm.sortbuf[t]);
         }
+        long long t4 = clock64();
         if (tid == 0 && a.stats) {
             atomicAdd(&a.stats[kStatRows], 1ull);
             atomicAdd(&a.stats[kStatPasses], (unsigned long long)passes);
@@ -383,6 +550,10 @@ __global__ __launch_bounds__(kSelThreads) void select_rows_kernel(SelectArgs a, 
             atomicAdd(&a.stats[kStatStreamPasses], (unsigned long long)stream_passes);
             atomicAdd(&a.stats[kStatSpillRows], (unsigned long long)spill);
             atomicAdd(&a.stats[kStatFirstSurvivors], (unsigned long long)first);
+            atomicAdd(&a.stats[kStatCycSample], (unsigned long long)cyc_sample);
+            atomicAdd(&a.stats[kStatCycStream], (unsigned long long)cyc_stream);
+            atomicAdd(&a.stats[kStatCycSelect], (unsigned long long)(t3 - t2));
+            atomicAdd(&a.stats[kStatCycFinal], (unsigned long long)(t4 - t3));
         }
         __syncthreads();
     }
@@ -441,10 +612,15 @@ int select_cap_for_k(uint32_t k) {
 
 template <int CAP>
 static int blocks_per_cu() {
-    int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, select_rows_kernel<CAP>, kSelThreads, 0) != hipSuccess || n < 1)
-        n = 1;
-    return n;
+    static int cached = 0;  // the library targets one architecture, so one value per kernel
+    if (cached == 0) {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, select_rows_kernel<CAP>, kSelThreads, 0) != hipSuccess ||
+            n < 1)
+            n = 1;
+        cached = n;
+    }
+    return cached;
 }
 
 int select_grid(int cap, int64_t rows, int num_cu) {
