@@ -147,6 +147,56 @@ knn_status_t knn_partition(knn_handle_t h, const float *in, int64_t rows, int64_
                            int64_t ld, const float *piv_val, const int32_t *piv_idx,
                            float *out_val, int32_t *out_idx, int32_t *out_left, void *stream);
 
+/*
+ * knn_search -- for each of m queries, its k nearest corpus points by squared
+ * Euclidean distance (Methods, "Distance calculation": squared distance
+ * ||x||^2 + ||y||^2 - 2 x.y, ranked on ||y||^2 - 2 x.y since ||x||^2 is common
+ * to a row).  Candidates (oversample * k per row) are ranked on that reduced
+ * key from the matrix-core product, then re-ranked by the exact FP32 direct
+ * form sum_t (q_t - c_t)^2, which is what out_dist returns.
+ *
+ *   queries   m x d FP32                                           [in, device]
+ *   corpus    n x d FP32                                           [in, device]
+ *   k         1 <= k <= min(n, 1024)
+ *   out_dist  m x k FP32 squared distances                          [out]
+ *   out_idx   m x k int32 corpus indices                            [out]
+ * Errors: INVALID_VALUE for null pointers, m < 0, n < 1, d < 1, k < 1, k > n;
+ * UNSUPPORTED for k > 1024, n > INT32_MAX or an unsupported precision.
+ */
+knn_status_t knn_search(knn_handle_t h, const float *queries, int64_t m, const float *corpus,
+                        int64_t n, int32_t d, int32_t k, float *out_dist, int32_t *out_idx,
+                        void *stream, const knn_options_t *opt);
+
+/*
+ * knn_graph -- the k-NN graph of n points (Introduction: every corpus point is
+ * also a query).  Same as knn_search(points, n, points, n, ...) except that each
+ * point's own index is excluded; duplicates at distance 0 remain neighbours.
+ *   points    n x d FP32                                           [in, device]
+ *   k         1 <= k <= min(n - 1, 1024)
+ * Errors: as knn_search, with k > n - 1 rejected.
+ */
+knn_status_t knn_graph(knn_handle_t h, const float *points, int64_t n, int32_t d, int32_t k,
+                       float *out_dist, int32_t *out_idx, void *stream,
+                       const knn_options_t *opt);
+
+/*
+ * knn_distances -- the m x n matrix of squared Euclidean distances between the
+ * rows of `queries` and `corpus` by the norm expansion
+ * ||q||^2 + ||c||^2 - 2 q.c (Methods, "Distance calculation": norms by a
+ * reduction, dot products as one matrix product on the FP32 matrix cores).
+ * Together with knn_select_k this is the paper's two-step pipeline with the
+ * matrix stored.  Values carry the cancellation error of the expansion and can
+ * be slightly negative for near-duplicate points.
+ *
+ *   queries  m x d FP32                                            [in, device]
+ *   corpus   n x d FP32                                            [in, device]
+ *   out      m x n FP32, row stride ldo (>= n)                     [out]
+ * Errors: INVALID_VALUE for null pointers, m < 0, n < 1, d < 1, ldo < n;
+ * UNSUPPORTED for n > INT32_MAX.
+ */
+knn_status_t knn_distances(knn_handle_t h, const float *queries, int64_t m, const float *corpus,
+                           int64_t n, int32_t d, float *out, int64_t ldo, void *stream);
+
 /* Counters of the last select / search / graph call on `h`.  Synchronises the
  * stream that call used. */
 knn_status_t knn_get_stats(knn_handle_t h, knn_stats_t *out);

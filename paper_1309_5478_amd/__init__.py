@@ -126,6 +126,20 @@ class Handle:
                                         self._stream(), ctypes.byref(o)))
         return dist, idx
 
+    def distances(self, queries, corpus):
+        """Squared Euclidean distance matrix [m, n] f32 by the norm expansion."""
+        torch = _torch()
+        for t in (queries, corpus):
+            if t.dim() != 2 or t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+                raise ValueError("queries and corpus must be contiguous 2-D float32 device tensors")
+        m, d = queries.shape
+        n = corpus.shape[0]
+        out = torch.empty((m, n), dtype=torch.float32, device=queries.device)
+        self._check(self.lib.knn_distances(self.h, ctypes.c_void_p(queries.data_ptr()), m,
+                                           ctypes.c_void_p(corpus.data_ptr()), n, d,
+                                           ctypes.c_void_p(out.data_ptr()), n, self._stream()))
+        return out
+
     def graph(self, points, k: int, pivot="sample", precision="fp32", oversample=4, flags=0):
         """k-NN graph of the rows of `points` (own index excluded).
         Returns (dist [n, k] f32, idx [n, k] i32)."""

@@ -52,6 +52,7 @@ PROTOTYPES = {
     "knn_partition": (_ST, [_P, _P, _I64, _I64, _I64, _P, _P, _P, _P, _P, _P]),
     "knn_search": (_ST, [_P, _P, _I64, _P, _I64, _I32, _I32, _P, _P, _P, ctypes.POINTER(Options)]),
     "knn_graph": (_ST, [_P, _P, _I64, _I32, _I32, _P, _P, _P, ctypes.POINTER(Options)]),
+    "knn_distances": (_ST, [_P, _P, _I64, _P, _I64, _I32, _P, _I64, _P]),
     "knn_get_stats": (_ST, [_P, ctypes.POINTER(Stats)]),
 }
 

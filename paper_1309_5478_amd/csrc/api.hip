@@ -7,6 +7,7 @@
 #include <mutex>
 #include <string>
 
+#include "dist.hpp"
 #include "internal.hpp"
 #include "knn.h"
 
@@ -22,6 +23,8 @@ struct knn_handle_s {
     hipStream_t last_stream = nullptr;
     knn_stats_t last{};
     bool stats_pending = false;
+    int64_t host_rows = 0, host_fallback = 0;  // host-side counters of the last call
+    uint32_t *pinned = nullptr;                 // one pinned word for device-to-host counts
     std::string err;
     int grid_cache[3] = {0, 0, 0};  // blocks per CU per select capacity class
 };
@@ -39,6 +42,18 @@ static knn_status_t hip_fail(knn_handle_t h, hipError_t e, const char *what) {
 }
 
 namespace knn {
+knn_status_t run_search(knn_handle_t h, const float *Q, int64_t m, const float *C, int64_t n, int d, int k, bool graph,
+                        float *out_dist, int32_t *out_idx, hipStream_t stream, const knn_options_t *opt);
+
+knn_status_t fail_msg(knn_handle_t h, knn_status_t s, const std::string &msg) { return fail(h, s, msg); }
+uint32_t *host_counter(knn_handle_t h) { return h->pinned; }
+unsigned long long *stats_ptr(knn_handle_t h) { return h->stats_dev; }
+int handle_num_cu(knn_handle_t h) { return h->num_cu; }
+void add_host_stats(knn_handle_t h, int64_t rows, int64_t fallback_rows) {
+    h->host_rows += rows;
+    h->host_fallback += fallback_rows;
+}
+
 // Ensures the handle's workspace holds at least `bytes`; returns its pointer.
 knn_status_t ensure_ws(knn_handle_t h, size_t bytes, hipStream_t stream, void **out) {
     if (bytes <= h->ws_bytes) {
@@ -107,6 +122,11 @@ knn_status_t knn_create(knn_handle_t *out, int device) {
         delete h;
         return hip_fail(nullptr, e, "hipMalloc(stats)");
     }
+    if ((e = hipHostMalloc(&h->pinned, sizeof(uint32_t), hipHostMallocDefault)) != hipSuccess) {
+        hipFree(h->stats_dev);
+        delete h;
+        return hip_fail(nullptr, e, "hipHostMalloc");
+    }
     *out = h;
     return KNN_SUCCESS;
 }
@@ -117,6 +137,7 @@ knn_status_t knn_destroy(knn_handle_t h) {
     hipDeviceSynchronize();
     if (h->ws) hipFree(h->ws);
     if (h->stats_dev) hipFree(h->stats_dev);
+    if (h->pinned) hipHostFree(h->pinned);
     delete h;
     return KNN_SUCCESS;
 }
@@ -126,6 +147,8 @@ static knn_status_t begin_stats(knn_handle_t h, hipStream_t stream) {
     if (e != hipSuccess) return hip_fail(h, e, "stats reset");
     h->last_stream = stream;
     h->stats_pending = true;
+    h->host_rows = 0;
+    h->host_fallback = 0;
     return KNN_SUCCESS;
 }
 
@@ -187,6 +210,94 @@ knn_status_t knn_partition(knn_handle_t h, const float *in, int64_t rows, int64_
     return KNN_SUCCESS;
 }
 
+static knn_status_t check_points(knn_handle_t h, const char *fn, const float *p, int64_t n, int32_t d) {
+    if (n < 1) return fail(h, KNN_ERROR_INVALID_VALUE, std::string(fn) + ": corpus size < 1");
+    if (d < 1) return fail(h, KNN_ERROR_INVALID_VALUE, std::string(fn) + ": d < 1");
+    if (!p) return fail(h, KNN_ERROR_INVALID_VALUE, std::string(fn) + ": null pointer");
+    if (n > INT32_MAX) return fail(h, KNN_ERROR_UNSUPPORTED, std::string(fn) + ": corpus larger than INT32_MAX");
+    return KNN_SUCCESS;
+}
+
+static knn_status_t check_options(knn_handle_t h, const char *fn, const knn_options_t *opt) {
+    if (!opt) return KNN_SUCCESS;
+    if (opt->pivot < KNN_PIVOT_PLAIN || opt->pivot > KNN_PIVOT_LEARNED)
+        return fail(h, KNN_ERROR_INVALID_VALUE, std::string(fn) + ": bad pivot mode");
+    if (opt->oversample < 0) return fail(h, KNN_ERROR_INVALID_VALUE, std::string(fn) + ": oversample < 0");
+    if (opt->precision < KNN_PREC_FP32 || opt->precision > KNN_PREC_FP8_E4M3)
+        return fail(h, KNN_ERROR_INVALID_VALUE, std::string(fn) + ": bad precision");
+    if (opt->precision != KNN_PREC_FP32)
+        return fail(h, KNN_ERROR_UNSUPPORTED, std::string(fn) + ": only FP32 inputs are implemented");
+    return KNN_SUCCESS;
+}
+
+knn_status_t knn_search(knn_handle_t h, const float *queries, int64_t m, const float *corpus, int64_t n, int32_t d,
+                        int32_t k, float *out_dist, int32_t *out_idx, void *stream_, const knn_options_t *opt) {
+    if (!h) return fail(nullptr, KNN_ERROR_INVALID_VALUE, "knn_search: handle is null");
+    if (m < 0) return fail(h, KNN_ERROR_INVALID_VALUE, "knn_search: m < 0");
+    knn_status_t st = check_points(h, "knn_search", corpus, n, d);
+    if (st != KNN_SUCCESS) return st;
+    if (k < 1) return fail(h, KNN_ERROR_INVALID_VALUE, "knn_search: k < 1");
+    if (k > n) return fail(h, KNN_ERROR_INVALID_VALUE, "knn_search: k > n");
+    if (k > kSelectMaxK) return fail(h, KNN_ERROR_UNSUPPORTED, "knn_search: k > 1024");
+    if ((st = check_options(h, "knn_search", opt)) != KNN_SUCCESS) return st;
+    if (m == 0) return KNN_SUCCESS;
+    if (!queries || !out_dist || !out_idx) return fail(h, KNN_ERROR_INVALID_VALUE, "knn_search: null pointer");
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    hipSetDevice(h->device);
+    if ((st = begin_stats(h, stream)) != KNN_SUCCESS) return st;
+    return run_search(h, queries, m, corpus, n, d, k, false, out_dist, out_idx, stream, opt);
+}
+
+knn_status_t knn_graph(knn_handle_t h, const float *points, int64_t n, int32_t d, int32_t k, float *out_dist,
+                       int32_t *out_idx, void *stream_, const knn_options_t *opt) {
+    if (!h) return fail(nullptr, KNN_ERROR_INVALID_VALUE, "knn_graph: handle is null");
+    knn_status_t st = check_points(h, "knn_graph", points, n, d);
+    if (st != KNN_SUCCESS) return st;
+    if (k < 1) return fail(h, KNN_ERROR_INVALID_VALUE, "knn_graph: k < 1");
+    if (k > n - 1) return fail(h, KNN_ERROR_INVALID_VALUE, "knn_graph: k > n - 1");
+    if (k > kSelectMaxK) return fail(h, KNN_ERROR_UNSUPPORTED, "knn_graph: k > 1024");
+    if ((st = check_options(h, "knn_graph", opt)) != KNN_SUCCESS) return st;
+    if (!out_dist || !out_idx) return fail(h, KNN_ERROR_INVALID_VALUE, "knn_graph: null pointer");
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    hipSetDevice(h->device);
+    if ((st = begin_stats(h, stream)) != KNN_SUCCESS) return st;
+    return run_search(h, points, n, points, n, d, k, true, out_dist, out_idx, stream, opt);
+}
+
+knn_status_t knn_distances(knn_handle_t h, const float *queries, int64_t m, const float *corpus, int64_t n, int32_t d,
+                           float *out, int64_t ldo, void *stream_) {
+    if (!h) return fail(nullptr, KNN_ERROR_INVALID_VALUE, "knn_distances: handle is null");
+    if (m < 0) return fail(h, KNN_ERROR_INVALID_VALUE, "knn_distances: m < 0");
+    knn_status_t st = check_points(h, "knn_distances", corpus, n, d);
+    if (st != KNN_SUCCESS) return st;
+    if (ldo < n) return fail(h, KNN_ERROR_INVALID_VALUE, "knn_distances: ldo < n");
+    if (m == 0) return KNN_SUCCESS;
+    if (!queries || !out) return fail(h, KNN_ERROR_INVALID_VALUE, "knn_distances: null pointer");
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    hipSetDevice(h->device);
+    void *ws = nullptr;
+    size_t need = (size_t)(m + n) * sizeof(float) + 512;
+    if ((st = ensure_ws(h, need, stream, &ws)) != KNN_SUCCESS) return st;
+    float *qn = static_cast<float *>(ws);
+    float *cn = qn + ((m + 63) / 64) * 64;
+    hipError_t e;
+    if ((e = launch_sqnorm(queries, m, d, qn, stream)) != hipSuccess) return hip_fail(h, e, "norm kernel");
+    if ((e = launch_sqnorm(corpus, n, d, cn, stream)) != hipSuccess) return hip_fail(h, e, "norm kernel");
+    DistArgs a{};
+    a.Q = queries;
+    a.m = m;
+    a.C = corpus;
+    a.n = n;
+    a.d = d;
+    a.cnorm = cn;
+    a.qnorm = qn;
+    a.self_offset = -1;
+    a.out = out;
+    a.ldo = ldo;
+    if ((e = launch_dist_gemm(a, kEpiDense, stream)) != hipSuccess) return hip_fail(h, e, "distance kernel");
+    return KNN_SUCCESS;
+}
+
 knn_status_t knn_get_stats(knn_handle_t h, knn_stats_t *out) {
     if (!h || !out) return fail(h, KNN_ERROR_INVALID_VALUE, "knn_get_stats: null argument");
     hipSetDevice(h->device);
@@ -205,7 +316,8 @@ knn_status_t knn_get_stats(knn_handle_t h, knn_stats_t *out) {
         t.stream_passes_total = (int64_t)s[kStatStreamPasses];
         t.spill_rows = (int64_t)s[kStatSpillRows];
         t.first_pass_survivors = (int64_t)s[kStatFirstSurvivors];
-        t.fallback_rows = (int64_t)s[kStatFallbackRows];
+        t.fallback_rows = (int64_t)s[kStatFallbackRows] + h->host_fallback;
+        if (t.rows == 0) t.rows = h->host_rows;
         t.candidates_total = (int64_t)s[kStatCandidates];
         t.phase_cycles[0] = (int64_t)s[kStatCycSample];
         t.phase_cycles[1] = (int64_t)s[kStatCycStream];

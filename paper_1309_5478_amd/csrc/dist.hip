@@ -1,0 +1,405 @@
+// Distance kernels (Methods, "Distance calculation"): squared norms, the
+// matrix-core product of queries and corpus, the reduced key
+// d'_ij = ||c_j||^2 - 2 q_i . c_j (the per-row constant ||q_i||^2 dropped), and the
+// exact direct-form re-rank of the surviving candidates.
+//
+// GEMM: FP32 inputs on v_mfma_f32_32x32x2f32, FP32 accumulation.  A workgroup of
+// WM x WN waves computes a (64 WM) x (64 WN) tile; each wave a 64 x 64 block as
+// 2 x 2 MFMA blocks of 32 x 32.  Operands are staged through LDS in 32-wide
+// k-chunks (row-major, stride 36 floats so that 16-byte fragment reads are
+// bank-conflict free), double-buffered: the next chunk's global loads are in
+// flight while the current chunk feeds the matrix cores.  Each 16-byte LDS read
+// supplies one operand for four consecutive MFMAs (lane half h of MFMA q holds
+// k = 8s + 4h + q).
+//
+// Epilogues: DENSE writes d' (a materialised distance block); FILTER keeps only
+// d' <= tau_i and appends (d', j) keys to a per-row candidate list, one global
+// reservation per 32-lane half-row per MFMA register.
+#include "dist.hpp"
+#include "keys.hpp"
+
+namespace knn {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kBK = 32;       // k-chunk
+constexpr int kLdsStride = 36;  // floats per staged row
+
+template <int WM, int WN>
+struct GemmSmem {
+    float A[2][64 * WM][kLdsStride];
+    float B[2][64 * WN][kLdsStride];
+    float tau[64 * WM];
+    int64_t qid[64 * WM];  // global id of each query row (self exclusion), -1 if none
+    float qn[64 * WM];
+    float cn[64 * WN];
+};
+
+// XCD-aware tile order: workgroups are dispatched round-robin over the eight
+// XCDs, so block b runs on XCD b % 8.  Each XCD gets a contiguous range of tile
+// ids, walked in groups of G query tiles across the corpus tiles, so that the
+// workgroups resident on one XCD share A and B tiles in that XCD's L2.
+__device__ __forceinline__ void tile_of_block(uint32_t b, uint32_t tiles_m, uint32_t tiles_n, uint32_t &tm,
+                                              uint32_t &tn, bool &valid) {
+    const uint32_t T = tiles_m * tiles_n;
+    const uint32_t per = (T + 7) / 8;
+    uint32_t t = (b % 8) * per + b / 8;
+    valid = t < T;
+    if (!valid) return;
+    constexpr uint32_t G = 4;
+    uint32_t group = t / (G * tiles_n);
+    uint32_t first = group * G;
+    uint32_t gsize = tiles_m - first < G ? tiles_m - first : G;
+    uint32_t in = t - group * G * tiles_n;
+    tm = first + in % gsize;
+    tn = in / gsize;
+}
+
+template <int WM, int WN, bool VEC>
+__device__ __forceinline__ void load_chunk(const DistArgs &a, uint32_t row0, uint32_t col0, uint32_t kc, f32x4 *ra,
+                                           f32x4 *rb) {
+    constexpr int NT = 64 * WM * WN;
+    constexpr int A4 = 64 * WM * (kBK / 4) / NT;  // float4 loads per thread for A
+    constexpr int B4 = 64 * WN * (kBK / 4) / NT;
+    const uint32_t tid = threadIdx.x;
+#pragma unroll
+    for (int x = 0; x < A4; ++x) {
+        uint32_t f = tid + NT * x, r = f / (kBK / 4), c = f % (kBK / 4);
+        uint32_t gi = row0 + r, k0 = kc * kBK + c * 4;
+        f32x4 v = {0.f, 0.f, 0.f, 0.f};
+        if (gi < a.m) {
+            const float *p = a.Q + (int64_t)gi * a.d + k0;
+            if (VEC) {
+                if (k0 < (uint32_t)a.d) v = *reinterpret_cast<const f32x4 *>(p);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (k0 + e < (uint32_t)a.d) v[e] = p[e];
+            }
+        }
+        ra[x] = v;
+    }
+#pragma unroll
+    for (int x = 0; x < B4; ++x) {
+        uint32_t f = tid + NT * x, r = f / (kBK / 4), c = f % (kBK / 4);
+        uint32_t gj = col0 + r, k0 = kc * kBK + c * 4;
+        f32x4 v = {0.f, 0.f, 0.f, 0.f};
+        if (gj < a.n) {
+            const float *p = a.C + (int64_t)gj * a.d + k0;
+            if (VEC) {
+                if (k0 < (uint32_t)a.d) v = *reinterpret_cast<const f32x4 *>(p);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (k0 + e < (uint32_t)a.d) v[e] = p[e];
+            }
+        }
+        rb[x] = v;
+    }
+}
+
+template <int WM, int WN>
+__device__ __forceinline__ void store_chunk(GemmSmem<WM, WN> &sm, int buf, const f32x4 *ra, const f32x4 *rb) {
+    constexpr int NT = 64 * WM * WN;
+    constexpr int A4 = 64 * WM * (kBK / 4) / NT;
+    constexpr int B4 = 64 * WN * (kBK / 4) / NT;
+    const uint32_t tid = threadIdx.x;
+#pragma unroll
+    for (int x = 0; x < A4; ++x) {
+        uint32_t f = tid + NT * x, r = f / (kBK / 4), c = f % (kBK / 4);
+        *reinterpret_cast<f32x4 *>(&sm.A[buf][r][c * 4]) = ra[x];
+    }
+#pragma unroll
+    for (int x = 0; x < B4; ++x) {
+        uint32_t f = tid + NT * x, r = f / (kBK / 4), c = f % (kBK / 4);
+        *reinterpret_cast<f32x4 *>(&sm.B[buf][r][c * 4]) = rb[x];
+    }
+}
+
+template <int WM, int WN, int EPI, bool VEC>
+__global__ __launch_bounds__(64 * WM * WN) void dist_gemm_kernel(DistArgs a) {
+    constexpr int NT = 64 * WM * WN;
+    constexpr int BM = 64 * WM, BN = 64 * WN;
+    constexpr int A4 = BM * (kBK / 4) / NT;
+    constexpr int B4 = BN * (kBK / 4) / NT;
+    static_assert(A4 >= 1 && B4 >= 1, "tile too small for the thread count");
+    __shared__ GemmSmem<WM, WN> sm;
+
+    uint32_t tm, tn;
+    bool valid;
+    tile_of_block(blockIdx.x, a.tiles_m, a.tiles_n, tm, tn, valid);
+    if (!valid) return;  // whole workgroup leaves together
+    const uint32_t row0 = tm * BM, col0 = tn * BN;
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    const uint32_t wm = wave % WM, wn = wave / WM;
+    const uint32_t h = lane / 32, l32 = lane % 32;
+
+    // per-row thresholds and per-column norms for the epilogue
+    for (uint32_t t = tid; t < (uint32_t)BM; t += NT) {
+        uint32_t gi = row0 + t;
+        sm.tau[t] = (EPI == kEpiFilter && gi < a.m) ? a.tau[(int64_t)gi * a.tau_stride] : 0.f;
+        sm.qn[t] = (a.qnorm && gi < a.m) ? a.qnorm[gi] : 0.f;
+        sm.qid[t] = (a.self_offset >= 0 && gi < a.m) ? a.self_offset + (a.row_ids ? (int64_t)a.row_ids[gi] : (int64_t)gi)
+                                                     : (int64_t)-1;
+    }
+    for (uint32_t t = tid; t < (uint32_t)BN; t += NT) {
+        uint32_t gj = col0 + t;
+        sm.cn[t] = gj < a.n ? a.cnorm[gj] : 0.f;
+    }
+
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    const uint32_t nk = ((uint32_t)a.d + kBK - 1) / kBK;
+    f32x4 ra[A4], rb[B4];
+    load_chunk<WM, WN, VEC>(a, row0, col0, 0, ra, rb);
+    store_chunk<WM, WN>(sm, 0, ra, rb);
+    __syncthreads();
+
+    for (uint32_t kc = 0; kc < nk; ++kc) {
+        const int cur = kc & 1;
+        if (kc + 1 < nk) load_chunk<WM, WN, VEC>(a, row0, col0, kc + 1, ra, rb);
+#pragma unroll
+        for (int s = 0; s < kBK / 8; ++s) {
+            f32x4 fa[2], fb[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+                fa[i] = *reinterpret_cast<const f32x4 *>(&sm.A[cur][wm * 64 + i * 32 + l32][8 * s + 4 * h]);
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                fb[j] = *reinterpret_cast<const f32x4 *>(&sm.B[cur][wn * 64 + j * 32 + l32][8 * s + 4 * h]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[i][q], fb[j][q], acc[i][j], 0, 0, 0);
+        }
+        if (kc + 1 < nk) store_chunk<WM, WN>(sm, cur ^ 1, ra, rb);
+        __syncthreads();
+    }
+
+    // epilogue: element (i, j) of block (bi, bj), register r, lane l:
+    //   row = wm*64 + bi*32 + 8*(r/4) + 4*h + r%4, col = wn*64 + bj*32 + l%32
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+        const uint32_t cl = wn * 64 + bj * 32 + l32;
+        const uint32_t gj = col0 + cl;
+        const float cn = sm.cn[cl];
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const uint32_t rl = wm * 64 + bi * 32 + 8 * (r / 4) + 4 * h + (r % 4);
+                const uint32_t gi = row0 + rl;
+                const float dp = fmaf(-2.0f, acc[bi][bj][r], cn);
+                const bool in = (gi < a.m) & (gj < a.n);
+                const bool self = (int64_t)gj == sm.qid[rl];
+                if (EPI == kEpiDense) {
+                    // with query norms: ||q||^2 + ||c||^2 - 2 q.c; without: the reduced key d'
+                    const float v = a.qnorm ? fmaf(-2.0f, acc[bi][bj][r], sm.qn[rl] + cn) : dp;
+                    if (in) a.out[(int64_t)gi * a.ldo + gj] = self ? __uint_as_float(0x7f800000u) : v;
+                } else {
+                    const bool pass = in & !self & (dp <= sm.tau[rl]);
+                    const uint64_t m = __ballot(pass);
+                    if (m) {
+                        const uint32_t half = h ? (uint32_t)(m >> 32) : (uint32_t)m;
+                        uint32_t v = 0;
+                        if (l32 == 0 && half) v = atomicAdd(&a.cnt[gi], (uint32_t)__popc(half));
+                        const uint32_t b0 = __shfl(v, 0), b1 = __shfl(v, 32);
+                        if (pass) {
+                            const uint32_t below = lanes_below(m) - (h ? (uint32_t)__popc((uint32_t)m) : 0u);
+                            const uint32_t slot = (h ? b1 : b0) + below;
+                            if (slot < (uint32_t)a.cap) a.cand[(int64_t)gi * a.cap + slot] = make_key(dp, gj);
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ---- squared norms, one wave per point, fixed lane-tree order -------------
+__global__ __launch_bounds__(256) void sqnorm_kernel(const float *__restrict__ X, int64_t n, int d,
+                                                     float *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.x / kWave;
+    if (i >= n) return;
+    const uint32_t lane = lane_id();
+    const float *x = X + i * d;
+    float s = 0.f;
+    for (int t = lane; t < d; t += kWave) s = fmaf(x[t], x[t], s);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) out[i] = s;
+}
+
+// ---- gather rows (and their norms) -----------------------------------------
+// dst row t = src row idx[t] (idx null: row floor(t * n / rows)).
+__global__ __launch_bounds__(256) void gather_rows_kernel(const float *__restrict__ src, int64_t n, int d,
+                                                          const int32_t *__restrict__ idx, int64_t rows,
+                                                          float *__restrict__ dst, const float *__restrict__ norms,
+                                                          float *__restrict__ dst_norms) {
+    const int64_t t = (int64_t)blockIdx.x * 4 + threadIdx.x / kWave;
+    if (t >= rows) return;
+    const int64_t s = idx ? (int64_t)idx[t] : (t * n) / rows;
+    const uint32_t lane = lane_id();
+    for (int c = lane; c < d; c += kWave) dst[t * d + c] = src[s * d + c];
+    if (norms && lane == 0) dst_norms[t] = norms[s];
+}
+
+// ---- candidate bookkeeping ----------------------------------------------------
+// Rows whose candidate count is below `need` or above `cap` are listed for the
+// exact fallback.
+__global__ __launch_bounds__(256) void flag_rows_kernel(const uint32_t *__restrict__ cnt, int64_t m, uint32_t need,
+                                                        uint32_t cap, int force, uint32_t *__restrict__ nflag,
+                                                        int32_t *__restrict__ flags) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const uint32_t c = cnt[i];
+    if (force || c < need || c > cap) {
+        uint32_t p = atomicAdd(nflag, 1u);
+        flags[p] = (int32_t)i;
+    }
+}
+
+// Replaces the candidate lists of the flagged rows by the exact selection made
+// on their materialised distance rows.
+__global__ __launch_bounds__(256) void scatter_fallback_kernel(const int32_t *__restrict__ rows, int64_t nrows,
+                                                               const float *__restrict__ val,
+                                                               const int32_t *__restrict__ idx, int kk,
+                                                               uint64_t *__restrict__ cand, uint32_t *__restrict__ cnt,
+                                                               int cap) {
+    const int64_t f = blockIdx.x;
+    if (f >= nrows) return;
+    const int64_t i = rows[f];
+    for (int t = threadIdx.x; t < kk; t += blockDim.x)
+        cand[i * cap + t] = make_key(val[f * kk + t], (uint32_t)idx[f * kk + t]);
+    if (threadIdx.x == 0) cnt[i] = (uint32_t)kk;
+}
+
+// ---- exact re-rank ----------------------------------------------------------
+// One workgroup per query: the exact FP32 squared distance sum_t (q_t - c_t)^2
+// to each of the row's kk candidates (each lane accumulates its strided
+// elements in order, then a fixed xor-shuffle tree), then an LDS bitonic sort
+// of (distance, index) keys; the first k are written.
+constexpr int kRerankThreads = 256;
+constexpr int kRerankMax = 1024;
+
+__global__ __launch_bounds__(kRerankThreads) void rerank_kernel(RerankArgs a) {
+    __shared__ uint64_t keys[kRerankMax];
+    const int64_t i = blockIdx.x;
+    if (i >= a.m) return;
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    const float *q = a.Q + i * a.d;
+    const uint32_t kk = a.kk;
+    const bool vec = (a.d % 4) == 0;
+    for (uint32_t c = wave; c < kk; c += kRerankThreads / kWave) {
+        const uint32_t j = (uint32_t)a.cidx[i * kk + c];
+        if ((int64_t)j >= a.n) {  // a missing candidate (never for valid lists)
+            if (lane == 0) keys[c] = kKeyMax;
+            continue;
+        }
+        const float *y = a.C + (int64_t)j * a.d;
+        float s = 0.f;
+        if (vec) {
+            for (int t = lane * 4; t < a.d; t += kWave * 4) {
+                f32x4 qv = *reinterpret_cast<const f32x4 *>(q + t);
+                f32x4 yv = *reinterpret_cast<const f32x4 *>(y + t);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    float df = qv[e] - yv[e];
+                    s = fmaf(df, df, s);
+                }
+            }
+        } else {
+            for (int t = lane; t < a.d; t += kWave) {
+                float df = q[t] - y[t];
+                s = fmaf(df, df, s);
+            }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        if (lane == 0) keys[c] = make_key(s, j);
+    }
+    const uint32_t kp2 = next_pow2(kk);
+    for (uint32_t t = kk + tid; t < kp2; t += kRerankThreads) keys[t] = kKeyMax;
+    __syncthreads();
+    block_bitonic_sort<kRerankThreads>(keys, kp2);
+    for (uint32_t t = tid; t < (uint32_t)a.k; t += kRerankThreads) {
+        const uint64_t key = t < kk ? keys[t] : kKeyMax;
+        if (key == kKeyMax) {
+            a.out_dist[i * a.k + t] = __uint_as_float(0x7f800000u);
+            a.out_idx[i * a.k + t] = -1;
+        } else {
+            a.out_dist[i * a.k + t] = ord_to_float(key_ord(key));
+            a.out_idx[i * a.k + t] = (int32_t)key_idx(key);
+        }
+    }
+}
+
+// ---- host launchers ----------------------------------------------------------
+template <int WM, int WN, int EPI>
+static hipError_t launch_gemm_t(const DistArgs &a0, hipStream_t stream) {
+    DistArgs a = a0;
+    constexpr int BM = 64 * WM, BN = 64 * WN;
+    a.tiles_m = (uint32_t)((a.m + BM - 1) / BM);
+    a.tiles_n = (uint32_t)((a.n + BN - 1) / BN);
+    uint64_t T = (uint64_t)a.tiles_m * a.tiles_n;
+    uint64_t grid = ((T + 7) / 8) * 8;
+    if (grid > 0x7fffffffull) return hipErrorInvalidValue;
+    if (a.d % 4 == 0)
+        hipLaunchKernelGGL((dist_gemm_kernel<WM, WN, EPI, true>), dim3((unsigned)grid), dim3(64 * WM * WN), 0, stream, a);
+    else
+        hipLaunchKernelGGL((dist_gemm_kernel<WM, WN, EPI, false>), dim3((unsigned)grid), dim3(64 * WM * WN), 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_dist_gemm(const DistArgs &a, int epi, hipStream_t stream) {
+    if (a.m == 0 || a.n == 0) return hipSuccess;
+    return epi == kEpiDense ? launch_gemm_t<2, 2, kEpiDense>(a, stream) : launch_gemm_t<2, 2, kEpiFilter>(a, stream);
+}
+
+hipError_t launch_sqnorm(const float *X, int64_t n, int d, float *out, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(sqnorm_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, stream, X, n, d, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_rows(const float *src, int64_t n, int d, const int32_t *idx, int64_t rows, float *dst,
+                              const float *norms, float *dst_norms, hipStream_t stream) {
+    if (rows == 0) return hipSuccess;
+    hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, stream, src, n, d, idx,
+                       rows, dst, norms, dst_norms);
+    return hipGetLastError();
+}
+
+hipError_t launch_flag_rows(const uint32_t *cnt, int64_t m, uint32_t need, uint32_t cap, int force, uint32_t *nflag,
+                            int32_t *flags, hipStream_t stream) {
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(flag_rows_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, stream, cnt, m, need, cap,
+                       force, nflag, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_fallback(const int32_t *rows, int64_t nrows, const float *val, const int32_t *idx, int kk,
+                                   uint64_t *cand, uint32_t *cnt, int cap, hipStream_t stream) {
+    if (nrows == 0) return hipSuccess;
+    hipLaunchKernelGGL(scatter_fallback_kernel, dim3((unsigned)nrows), dim3(256), 0, stream, rows, nrows, val, idx, kk,
+                       cand, cnt, cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_rerank(const RerankArgs &a, hipStream_t stream) {
+    if (a.m == 0) return hipSuccess;
+    if (a.kk > kRerankMax) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(rerank_kernel, dim3((unsigned)a.m), dim3(kRerankThreads), 0, stream, a);
+    return hipGetLastError();
+}
+
+}  // namespace knn

@@ -35,6 +35,10 @@ struct SelectArgs {
     float *out_val;        // rows x k
     int32_t *out_idx;      // rows x k
     const float *pivot_hint;  // per-row first-pivot values (learned mode) or null
+    // key-list rows instead of `dist`: row r holds min(key_cnt[r], cols) keys at
+    // keys + r * ld (cols must not exceed the kernel capacity)
+    const uint64_t *keys;
+    const uint32_t *key_cnt;
     int mode;              // PivotMode
     unsigned long long *stats;  // kStatCount counters, or null
 };
@@ -50,6 +54,9 @@ int select_grid(int cap, int64_t rows, int num_cu);
 size_t select_ws_bytes(int cap, uint32_t cols, int grid);
 // Launch; `ws` must hold select_ws_bytes(...) bytes.
 hipError_t launch_select(const SelectArgs &a, int cap, int grid, void *ws, hipStream_t stream);
+// Selection over key-list rows (a.keys / a.key_cnt set, a.cols <= kSelectKeysCap).
+constexpr int kSelectKeysCap = 4096;
+hipError_t launch_select_keys(const SelectArgs &a, int64_t rows_grid_limit, int num_cu, hipStream_t stream);
 
 // ---- one partition pass, one wavefront per row ------------------------------
 hipError_t launch_partition(const float *in, int64_t rows, uint32_t cols, int64_t ld,

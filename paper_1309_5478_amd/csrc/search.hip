@@ -1,0 +1,318 @@
+// Host orchestration of knn_search / knn_graph: brute-force k-NN by a distance
+// matrix product fused with per-row selection (Methods: "Distance calculation"
+// and "GPU-based quick multi-select"), on one device.
+//
+// Fused path, per block of query rows:
+//  1. threshold: d' to S strided corpus samples (a small dense product), then
+//     tau_i = the sample order statistic just above the expected rank of the
+//     kk-th candidate (kk = oversample * k), by quick multi-select over the
+//     sample row.  When the sample is the whole corpus, tau_i is the exact kk-th.
+//  2. fused product: the full Q x C product with the FILTER epilogue, which
+//     keeps d' <= tau_i in per-row candidate lists; the M x N matrix is never
+//     stored.
+//  3. rows with fewer than kk candidates (tau too low) or more than the list
+//     capacity are listed and re-done exactly: their distance rows are
+//     materialised and selected in full.
+//  4. quick multi-select of the kk smallest reduced keys among each row's
+//     candidates, then the exact FP32 direct-form re-rank of those kk and the
+//     final k, in (distance, index) order.
+// Unfused path (KNN_FLAG_UNFUSED): blocks of the distance matrix are
+// materialised and selected directly, then re-ranked the same way.
+#include <cmath>
+#include <string>
+
+#include "dist.hpp"
+#include "internal.hpp"
+#include "knn.h"
+
+namespace knn {
+
+knn_status_t ensure_ws(knn_handle_t h, size_t bytes, hipStream_t stream, void **out);
+knn_status_t fail_msg(knn_handle_t h, knn_status_t s, const std::string &msg);
+uint32_t *host_counter(knn_handle_t h);
+unsigned long long *stats_ptr(knn_handle_t h);
+void add_host_stats(knn_handle_t h, int64_t rows, int64_t fallback_rows);
+int handle_num_cu(knn_handle_t h);
+
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t stream);
+hipError_t launch_sum_u32(const uint32_t *p, int64_t n, unsigned long long *out, hipStream_t stream);
+
+namespace {
+
+// Bump allocator over one workspace buffer (sizing pass with base == nullptr).
+struct Carve {
+    char *base;
+    size_t off = 0;
+    template <class T>
+    T *take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T *p = reinterpret_cast<T *>(base ? base + off : nullptr);
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+constexpr int kSampleCols = 2048;
+constexpr int64_t kRowBlock = 32768;
+constexpr size_t kDenseBytes = size_t(1) << 30;  // materialised distance block budget
+
+struct Plan {
+    int64_t m, n, n_eff;
+    int d, k, kk;
+    bool graph, unfused;
+    int force;
+    // fused
+    int S;
+    bool gathered;
+    int r;
+    int cap;
+    int64_t Mb;
+    int64_t Fb;
+    // unfused
+    int64_t Mu;
+};
+
+struct Bufs {
+    float *cnorm = nullptr;
+    float *Cs = nullptr, *csn = nullptr;
+    float *Ds = nullptr, *tv = nullptr;
+    int32_t *ti = nullptr;
+    uint32_t *cnt = nullptr;
+    uint64_t *cand = nullptr;
+    int32_t *flags = nullptr;
+    uint32_t *nflag = nullptr;
+    float *sv = nullptr;
+    int32_t *si = nullptr;
+    float *Qf = nullptr, *Df = nullptr, *fv = nullptr;
+    int32_t *fi = nullptr;
+    float *Dm = nullptr;
+    void *selws = nullptr;
+};
+
+size_t carve(Carve &c, const Plan &p, Bufs &b, int num_cu) {
+    b.cnorm = c.take<float>(p.n);
+    size_t selws = 0;
+    if (p.unfused) {
+        b.Dm = c.take<float>((size_t)p.Mu * p.n);
+        b.sv = c.take<float>((size_t)p.Mu * p.kk);
+        b.si = c.take<int32_t>((size_t)p.Mu * p.kk);
+        int cap = select_cap_for_k(p.kk);
+        selws = select_ws_bytes(cap, (uint32_t)p.n, select_grid(cap, p.Mu, num_cu));
+    } else {
+        if (p.gathered) {
+            b.Cs = c.take<float>((size_t)p.S * p.d);
+            b.csn = c.take<float>(p.S);
+        }
+        b.Ds = c.take<float>((size_t)p.Mb * p.S);
+        b.tv = c.take<float>((size_t)p.Mb * (p.r + 1));
+        b.ti = c.take<int32_t>((size_t)p.Mb * (p.r + 1));
+        b.cnt = c.take<uint32_t>(p.Mb);
+        b.cand = c.take<uint64_t>((size_t)p.Mb * p.cap);
+        b.flags = c.take<int32_t>(p.Mb);
+        b.nflag = c.take<uint32_t>(1);
+        b.sv = c.take<float>((size_t)p.Mb * p.kk);
+        b.si = c.take<int32_t>((size_t)p.Mb * p.kk);
+        b.Qf = c.take<float>((size_t)p.Fb * p.d);
+        b.Df = c.take<float>((size_t)p.Fb * p.n);
+        b.fv = c.take<float>((size_t)p.Fb * p.kk);
+        b.fi = c.take<int32_t>((size_t)p.Fb * p.kk);
+        int cap1 = select_cap_for_k(p.r + 1);
+        size_t w1 = select_ws_bytes(cap1, (uint32_t)p.S, select_grid(cap1, p.Mb, num_cu));
+        int cap2 = select_cap_for_k(p.kk);
+        size_t w2 = select_ws_bytes(cap2, (uint32_t)p.n, select_grid(cap2, p.Fb, num_cu));
+        selws = w1 > w2 ? w1 : w2;
+    }
+    b.selws = c.take<char>(selws < 256 ? 256 : selws);
+    return c.off;
+}
+
+hipError_t select_dense(const float *D, int64_t rows, int64_t cols, int64_t ld, int k, float *ov, int32_t *oi,
+                        void *ws, int num_cu, hipStream_t stream) {
+    SelectArgs a{};
+    a.dist = D;
+    a.rows = rows;
+    a.cols = (uint32_t)cols;
+    a.ld = ld;
+    a.k = (uint32_t)k;
+    a.out_val = ov;
+    a.out_idx = oi;
+    a.mode = kPivotSample;
+    int cap = select_cap_for_k((uint32_t)k);
+    return launch_select(a, cap, select_grid(cap, rows, num_cu), ws, stream);
+}
+
+}  // namespace
+
+knn_status_t run_search(knn_handle_t h, const float *Q, int64_t m, const float *C, int64_t n, int d, int k, bool graph,
+                        float *out_dist, int32_t *out_idx, hipStream_t stream, const knn_options_t *opt) {
+    const int num_cu = handle_num_cu(h);
+    Plan p{};
+    p.m = m;
+    p.n = n;
+    p.n_eff = graph ? n - 1 : n;
+    p.d = d;
+    p.k = k;
+    p.graph = graph;
+    int over = opt && opt->oversample > 0 ? opt->oversample : 4;
+    int64_t kk = (int64_t)k * over;
+    if (kk > kSelectMaxK) kk = kSelectMaxK;
+    if (kk < k) kk = k;
+    if (kk > p.n_eff) kk = p.n_eff;
+    p.kk = (int)kk;
+    p.unfused = opt && (opt->flags & KNN_FLAG_UNFUSED);
+    p.force = (opt && (opt->flags & KNN_FLAG_FORCE_FALLBACK)) ? 1 : 0;
+
+    if (p.unfused) {
+        int64_t mu = (int64_t)(kDenseBytes / sizeof(float) / (size_t)n);
+        p.Mu = mu < 1 ? 1 : (mu > m ? m : mu);
+    } else {
+        p.S = n < kSampleCols ? (int)n : kSampleCols;
+        p.gathered = n > p.S;
+        if (!p.gathered) {
+            p.r = p.kk - 1;  // the sample is the whole corpus (own index excluded)
+        } else {
+            double mu = (double)p.S * p.kk / (double)p.n_eff;
+            double r = std::ceil(mu + 3.0 * std::sqrt(mu) + 4.0);
+            int64_t ri = (int64_t)r;
+            if (ri > p.S - 1) ri = p.S - 1;
+            if (ri > kSelectMaxK - 1) ri = kSelectMaxK - 1;
+            p.r = (int)ri;
+        }
+        double expected = p.gathered ? (double)(p.r + 1) * (double)p.n_eff / p.S : (double)p.kk;
+        int64_t cap = (int64_t)(2.0 * expected);
+        if (cap < p.kk + 64) cap = p.kk + 64;
+        cap = (cap + 63) / 64 * 64;
+        if (cap > kSelectKeysCap) cap = kSelectKeysCap;
+        p.cap = (int)cap;
+        p.Mb = m < kRowBlock ? m : kRowBlock;
+        int64_t fb = (int64_t)((size_t(256) << 20) / sizeof(float) / (size_t)n);
+        p.Fb = fb < 1 ? 1 : (fb > p.Mb ? p.Mb : fb);
+    }
+
+    Bufs b;
+    Carve sizing{nullptr};
+    size_t bytes = carve(sizing, p, b, num_cu);
+    void *ws = nullptr;
+    knn_status_t st = ensure_ws(h, bytes, stream, &ws);
+    if (st != KNN_SUCCESS) return st;
+    Carve real{static_cast<char *>(ws)};
+    carve(real, p, b, num_cu);
+
+    hipError_t e;
+#define KNN_TRY(call)                                                                                   \
+    do {                                                                                                \
+        if ((e = (call)) != hipSuccess) return fail_msg(h, KNN_ERROR_DEVICE, std::string(#call) + ": " + \
+                                                                                 hipGetErrorString(e)); \
+    } while (0)
+
+    KNN_TRY(launch_sqnorm(C, n, d, b.cnorm, stream));
+    int64_t fallback_total = 0;
+
+    if (p.unfused) {
+        for (int64_t i0 = 0; i0 < m; i0 += p.Mu) {
+            const int64_t mb = m - i0 < p.Mu ? m - i0 : p.Mu;
+            DistArgs a{};
+            a.Q = Q + i0 * d;
+            a.m = mb;
+            a.C = C;
+            a.n = n;
+            a.d = d;
+            a.cnorm = b.cnorm;
+            a.self_offset = graph ? i0 : -1;
+            a.out = b.Dm;
+            a.ldo = n;
+            KNN_TRY(launch_dist_gemm(a, kEpiDense, stream));
+            KNN_TRY(select_dense(b.Dm, mb, n, n, p.kk, b.sv, b.si, b.selws, num_cu, stream));
+            RerankArgs rr{Q + i0 * d, mb, C, n, d, b.si, (uint32_t)p.kk, k, out_dist + i0 * k, out_idx + i0 * k};
+            KNN_TRY(launch_rerank(rr, stream));
+        }
+        add_host_stats(h, m, 0);
+        return KNN_SUCCESS;
+    }
+
+    const float *Cs = C, *csn = b.cnorm;
+    if (p.gathered) {
+        KNN_TRY(launch_gather_rows(C, n, d, nullptr, p.S, b.Cs, b.cnorm, b.csn, stream));
+        Cs = b.Cs;
+        csn = b.csn;
+    }
+    uint32_t *hcount = host_counter(h);
+    for (int64_t i0 = 0; i0 < m; i0 += p.Mb) {
+        const int64_t mb = m - i0 < p.Mb ? m - i0 : p.Mb;
+        const float *Qb = Q + i0 * d;
+        // 1. thresholds from the sample
+        DistArgs sa{};
+        sa.Q = Qb;
+        sa.m = mb;
+        sa.C = Cs;
+        sa.n = p.S;
+        sa.d = d;
+        sa.cnorm = csn;
+        sa.self_offset = (graph && !p.gathered) ? i0 : -1;
+        sa.out = b.Ds;
+        sa.ldo = p.S;
+        KNN_TRY(launch_dist_gemm(sa, kEpiDense, stream));
+        KNN_TRY(select_dense(b.Ds, mb, p.S, p.S, p.r + 1, b.tv, b.ti, b.selws, num_cu, stream));
+        // 2. fused product + filter
+        KNN_TRY(launch_fill_u32(b.cnt, mb, 0u, stream));
+        DistArgs fa{};
+        fa.Q = Qb;
+        fa.m = mb;
+        fa.C = C;
+        fa.n = n;
+        fa.d = d;
+        fa.cnorm = b.cnorm;
+        fa.self_offset = graph ? i0 : -1;
+        fa.tau = b.tv + p.r;
+        fa.tau_stride = p.r + 1;
+        fa.cnt = b.cnt;
+        fa.cand = b.cand;
+        fa.cap = p.cap;
+        KNN_TRY(launch_dist_gemm(fa, kEpiFilter, stream));
+        KNN_TRY(launch_sum_u32(b.cnt, mb, stats_ptr(h) + kStatCandidates, stream));
+        // 3. exact re-do of rows whose candidate list is unusable
+        KNN_TRY(launch_fill_u32(b.nflag, 1, 0u, stream));
+        KNN_TRY(launch_flag_rows(b.cnt, mb, (uint32_t)p.kk, (uint32_t)p.cap, p.force, b.nflag, b.flags, stream));
+        KNN_TRY(hipMemcpyAsync(hcount, b.nflag, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
+        KNN_TRY(hipStreamSynchronize(stream));
+        const int64_t nf = *hcount;
+        fallback_total += nf;
+        for (int64_t f0 = 0; f0 < nf; f0 += p.Fb) {
+            const int64_t fb = nf - f0 < p.Fb ? nf - f0 : p.Fb;
+            KNN_TRY(launch_gather_rows(Qb, mb, d, b.flags + f0, fb, b.Qf, nullptr, nullptr, stream));
+            DistArgs da{};
+            da.Q = b.Qf;
+            da.m = fb;
+            da.C = C;
+            da.n = n;
+            da.d = d;
+            da.cnorm = b.cnorm;
+            da.self_offset = graph ? i0 : -1;
+            da.row_ids = b.flags + f0;
+            da.out = b.Df;
+            da.ldo = n;
+            KNN_TRY(launch_dist_gemm(da, kEpiDense, stream));
+            KNN_TRY(select_dense(b.Df, fb, n, n, p.kk, b.fv, b.fi, b.selws, num_cu, stream));
+            KNN_TRY(launch_scatter_fallback(b.flags + f0, fb, b.fv, b.fi, p.kk, b.cand, b.cnt, p.cap, stream));
+        }
+        // 4. kk smallest candidates, exact re-rank, final k
+        SelectArgs ka{};
+        ka.keys = b.cand;
+        ka.key_cnt = b.cnt;
+        ka.rows = mb;
+        ka.cols = (uint32_t)p.cap;
+        ka.ld = p.cap;
+        ka.k = (uint32_t)p.kk;
+        ka.out_val = b.sv;
+        ka.out_idx = b.si;
+        ka.mode = kPivotSample;
+        KNN_TRY(launch_select_keys(ka, mb, num_cu, stream));
+        RerankArgs rr{Qb, mb, C, n, d, b.si, (uint32_t)p.kk, k, out_dist + i0 * k, out_idx + i0 * k};
+        KNN_TRY(launch_rerank(rr, stream));
+    }
+#undef KNN_TRY
+    add_host_stats(h, m, fallback_total);
+    return KNN_SUCCESS;
+}
+
+}  // namespace knn

@@ -336,7 +336,7 @@ __device__ __forceinline__ uint64_t merge_rank(SelSmem<CAP> &sm, uint32_t r) {
     return mn;
 }
 
-template <int CAP>
+template <int CAP, bool KEYS>
 __global__ __launch_bounds__(kSelThreads) void select_rows_kernel(SelectArgs a, uint64_t *ws,
                                                                    uint64_t ws_slot) {
     __shared__ SelSmem<CAP> sm;
@@ -351,7 +351,15 @@ __global__ __launch_bounds__(kSelThreads) void select_rows_kernel(SelectArgs a, 
         long long cyc_sample = 0, cyc_stream = 0;
         uint32_t sb, ss, se, Kp;  // active segment (buffer, start, end) and keys still needed
 
-        if (N <= (uint32_t)CAP) {
+        if (KEYS) {
+            // key-list row (at most CAP keys, at least k of them)
+            const uint32_t c = a.key_cnt[r];
+            const uint32_t n = c < N ? c : N;
+            const uint64_t *src = a.keys + r * a.ld;
+            for (uint32_t p = tid; p < n; p += kSelThreads) sm.buf[0][p] = src[p];
+            __syncthreads();
+            sb = 0; ss = 0; se = n; Kp = k;
+        } else if (N <= (uint32_t)CAP) {
             for (uint32_t p = tid; p < N; p += kSelThreads) sm.buf[0][p] = make_key(row[p], p);
             __syncthreads();
             sb = 0; ss = 0; se = N; Kp = k;
@@ -525,7 +533,7 @@ __global__ __launch_bounds__(kSelThreads) void select_rows_kernel(SelectArgs a, 
                 v = __uint_as_float(0x7fc00000u);
                 idx = 0xFFFFFFFFu;
             } else {
-                v = (o == kOrdZero || o == kOrdNaN) ? row[idx] : ord_to_float(o);
+                v = (!KEYS && (o == kOrdZero || o == kOrdNaN)) ? row[idx] : ord_to_float(o);
             }
             a.out_val[r * k + t] = v;
             a.out_idx[r * k + t] = (int32_t)idx;
@@ -598,6 +606,22 @@ __global__ __launch_bounds__(256) void partition_rows_kernel(const float *__rest
     if (lane == 0) out_left[r] = (int32_t)g_lt;
 }
 
+__global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Adds the sum of n uint32 values to *out (one atomic per workgroup).
+__global__ __launch_bounds__(256) void sum_u32_kernel(const uint32_t *p, int64_t n, unsigned long long *out) {
+    __shared__ unsigned long long part[4];
+    unsigned long long s = 0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) s += p[i];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane_id() == 0) part[threadIdx.x / kWave] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(out, part[0] + part[1] + part[2] + part[3]);
+}
+
 __global__ void zero_u64_kernel(unsigned long long *p, int n) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0ull;
@@ -615,7 +639,7 @@ static int blocks_per_cu() {
     static int cached = 0;  // the library targets one architecture, so one value per kernel
     if (cached == 0) {
         int n = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, select_rows_kernel<CAP>, kSelThreads, 0) != hipSuccess ||
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, select_rows_kernel<CAP, false>, kSelThreads, 0) != hipSuccess ||
             n < 1)
             n = 1;
         cached = n;
@@ -639,11 +663,31 @@ hipError_t launch_select(const SelectArgs &a, int cap, int grid, void *ws, hipSt
     uint64_t slot = a.cols > (uint32_t)cap ? (uint64_t)a.cols - cap : 0;
     uint64_t *w = static_cast<uint64_t *>(ws);
     switch (cap) {
-        case 1024: hipLaunchKernelGGL(select_rows_kernel<1024>, dim3(grid), dim3(kSelThreads), 0, stream, a, w, slot); break;
-        case 2048: hipLaunchKernelGGL(select_rows_kernel<2048>, dim3(grid), dim3(kSelThreads), 0, stream, a, w, slot); break;
-        case 4096: hipLaunchKernelGGL(select_rows_kernel<4096>, dim3(grid), dim3(kSelThreads), 0, stream, a, w, slot); break;
+        case 1024: hipLaunchKernelGGL((select_rows_kernel<1024, false>), dim3(grid), dim3(kSelThreads), 0, stream, a, w, slot); break;
+        case 2048: hipLaunchKernelGGL((select_rows_kernel<2048, false>), dim3(grid), dim3(kSelThreads), 0, stream, a, w, slot); break;
+        case 4096: hipLaunchKernelGGL((select_rows_kernel<4096, false>), dim3(grid), dim3(kSelThreads), 0, stream, a, w, slot); break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_select_keys(const SelectArgs &a, int64_t rows_grid_limit, int num_cu, hipStream_t stream) {
+    if (a.cols > (uint32_t)kSelectKeysCap || a.k > (uint32_t)kSelectMaxK) return hipErrorInvalidValue;
+    static int per = 0;
+    if (per == 0) {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, select_rows_kernel<kSelectKeysCap, true>, kSelThreads, 0) !=
+                hipSuccess ||
+            n < 1)
+            n = 1;
+        per = n;
+    }
+    int64_t g = (int64_t)per * num_cu;
+    if (g > a.rows) g = a.rows;
+    if (g > rows_grid_limit) g = rows_grid_limit;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL((select_rows_kernel<kSelectKeysCap, true>), dim3((unsigned)g), dim3(kSelThreads), 0, stream, a,
+                       (uint64_t *)nullptr, (uint64_t)0);
     return hipGetLastError();
 }
 
@@ -654,6 +698,20 @@ hipError_t launch_partition(const float *in, int64_t rows, uint32_t cols, int64_
     int64_t blocks = (rows + waves_per_block - 1) / waves_per_block;
     hipLaunchKernelGGL(partition_rows_kernel, dim3((unsigned)blocks), dim3(waves_per_block * kWave), 0, stream, in,
                        rows, cols, ld, piv_val, piv_idx, out_val, out_idx, out_left);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_u32(const uint32_t *p, int64_t n, unsigned long long *out, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(sum_u32_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, p, n, out);
     return hipGetLastError();
 }
 
