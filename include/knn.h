@@ -82,6 +82,9 @@ typedef struct {
 #define KNN_FLAG_FORCE_FALLBACK 0x1
 /* Materialise distance tiles and select from them instead of the fused kernel. */
 #define KNN_FLAG_UNFUSED 0x2
+/* Time every launch of the distance product with HIP events on the call's
+ * stream and report it in knn_stats_t (product_ms, product_launches). */
+#define KNN_FLAG_TIMING 0x4
 
 typedef struct {
     int64_t rows;                 /* rows processed by the last call              */
@@ -95,6 +98,10 @@ typedef struct {
     int64_t candidates_total;     /* search / graph candidates, summed            */
     int64_t phase_cycles[4];      /* shader clocks summed over rows: first pivot, */
                                   /* streaming passes, on-chip passes, final sort */
+    double product_ms;            /* KNN_FLAG_TIMING: summed duration of the main  */
+    int64_t product_launches;     /* distance-product launches (fused or dense),   */
+    double product_flops;         /* their count, and their algorithmic flops      */
+                                  /* (2 * rows * cols * d each)                    */
 } knn_stats_t;
 
 /* Create a handle bound to HIP device `device` (must be gfx950). */

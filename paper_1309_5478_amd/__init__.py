@@ -11,7 +11,7 @@ import ctypes
 
 from . import _abi
 from ._abi import (PIVOT_LEARNED, PIVOT_PLAIN, PIVOT_SAMPLE, PREC_BF16, PREC_FP32,  # noqa: F401
-                   PREC_FP8_E4M3, FLAG_FORCE_FALLBACK, FLAG_UNFUSED, Options, Stats)
+                   PREC_FP8_E4M3, FLAG_FORCE_FALLBACK, FLAG_UNFUSED, FLAG_TIMING, Options, Stats)
 
 _PIVOTS = {"plain": PIVOT_PLAIN, "sample": PIVOT_SAMPLE, "learned": PIVOT_LEARNED}
 _PRECS = {"fp32": PREC_FP32, "bf16": PREC_BF16, "fp8": PREC_FP8_E4M3}

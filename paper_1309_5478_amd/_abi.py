@@ -17,6 +17,7 @@ PIVOT_PLAIN, PIVOT_SAMPLE, PIVOT_LEARNED = 0, 1, 2
 PREC_FP32, PREC_BF16, PREC_FP8_E4M3 = 0, 1, 2
 FLAG_FORCE_FALLBACK = 0x1
 FLAG_UNFUSED = 0x2
+FLAG_TIMING = 0x4
 
 
 class Options(ctypes.Structure):
@@ -29,11 +30,15 @@ class Stats(ctypes.Structure):
                 ("passes_max", ctypes.c_int32), ("reserved0", ctypes.c_int32),
                 ("stream_passes_total", ctypes.c_int64), ("spill_rows", ctypes.c_int64),
                 ("first_pass_survivors", ctypes.c_int64), ("fallback_rows", ctypes.c_int64),
-                ("candidates_total", ctypes.c_int64), ("phase_cycles", ctypes.c_int64 * 4)]
+                ("candidates_total", ctypes.c_int64), ("phase_cycles", ctypes.c_int64 * 4),
+                ("product_ms", ctypes.c_double), ("product_launches", ctypes.c_int64),
+                ("product_flops", ctypes.c_double)]
 
     def as_dict(self):
         d = {name: int(getattr(self, name)) for name, _ in self._fields_
-             if name not in ("reserved0", "phase_cycles")}
+             if name not in ("reserved0", "phase_cycles", "product_ms", "product_flops")}
+        d["product_ms"] = float(self.product_ms)
+        d["product_flops"] = float(self.product_flops)
         d["phase_cycles"] = [int(x) for x in self.phase_cycles]
         return d
 

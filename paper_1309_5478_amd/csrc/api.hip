@@ -24,6 +24,8 @@ struct knn_handle_s {
     knn_stats_t last{};
     bool stats_pending = false;
     int64_t host_rows = 0, host_fallback = 0;  // host-side counters of the last call
+    double host_product_ms = 0, host_product_flops = 0;
+    int64_t host_product_launches = 0;
     uint32_t *pinned = nullptr;                 // one pinned word for device-to-host counts
     std::string err;
     int grid_cache[3] = {0, 0, 0};  // blocks per CU per select capacity class
@@ -52,6 +54,11 @@ int handle_num_cu(knn_handle_t h) { return h->num_cu; }
 void add_host_stats(knn_handle_t h, int64_t rows, int64_t fallback_rows) {
     h->host_rows += rows;
     h->host_fallback += fallback_rows;
+}
+void add_product_time(knn_handle_t h, double ms, double flops) {
+    h->host_product_ms += ms;
+    h->host_product_flops += flops;
+    h->host_product_launches += 1;
 }
 
 // Ensures the handle's workspace holds at least `bytes`; returns its pointer.
@@ -149,6 +156,9 @@ static knn_status_t begin_stats(knn_handle_t h, hipStream_t stream) {
     h->stats_pending = true;
     h->host_rows = 0;
     h->host_fallback = 0;
+    h->host_product_ms = 0;
+    h->host_product_flops = 0;
+    h->host_product_launches = 0;
     return KNN_SUCCESS;
 }
 
@@ -318,6 +328,9 @@ knn_status_t knn_get_stats(knn_handle_t h, knn_stats_t *out) {
         t.first_pass_survivors = (int64_t)s[kStatFirstSurvivors];
         t.fallback_rows = (int64_t)s[kStatFallbackRows] + h->host_fallback;
         if (t.rows == 0) t.rows = h->host_rows;
+        t.product_ms = h->host_product_ms;
+        t.product_flops = h->host_product_flops;
+        t.product_launches = h->host_product_launches;
         t.candidates_total = (int64_t)s[kStatCandidates];
         t.phase_cycles[0] = (int64_t)s[kStatCycSample];
         t.phase_cycles[1] = (int64_t)s[kStatCycStream];

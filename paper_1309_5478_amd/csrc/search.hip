@@ -32,6 +32,7 @@ knn_status_t fail_msg(knn_handle_t h, knn_status_t s, const std::string &msg);
 uint32_t *host_counter(knn_handle_t h);
 unsigned long long *stats_ptr(knn_handle_t h);
 void add_host_stats(knn_handle_t h, int64_t rows, int64_t fallback_rows);
+void add_product_time(knn_handle_t h, double ms, double flops);
 int handle_num_cu(knn_handle_t h);
 
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t stream);
@@ -126,8 +127,43 @@ size_t carve(Carve &c, const Plan &p, Bufs &b, int num_cu) {
     return c.off;
 }
 
+// Optional HIP-event timing of the main distance-product launches.
+struct ProductTimer {
+    bool on = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    double flops = 0;
+    bool pending = false;
+    ~ProductTimer() {
+        if (e0) hipEventDestroy(e0);
+        if (e1) hipEventDestroy(e1);
+    }
+    hipError_t init(bool enable) {
+        on = enable;
+        if (!on) return hipSuccess;
+        hipError_t e = hipEventCreate(&e0);
+        if (e == hipSuccess) e = hipEventCreate(&e1);
+        return e;
+    }
+    hipError_t begin(hipStream_t s, double f) {
+        if (!on) return hipSuccess;
+        flops = f;
+        pending = true;
+        return hipEventRecord(e0, s);
+    }
+    hipError_t end(hipStream_t s) { return on ? hipEventRecord(e1, s) : hipSuccess; }
+    // after the stream has been synchronised past end()
+    hipError_t collect(knn_handle_t h) {
+        if (!on || !pending) return hipSuccess;
+        float ms = 0;
+        hipError_t e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess) add_product_time(h, ms, flops);
+        pending = false;
+        return e;
+    }
+};
+
 hipError_t select_dense(const float *D, int64_t rows, int64_t cols, int64_t ld, int k, float *ov, int32_t *oi,
-                        void *ws, int num_cu, hipStream_t stream) {
+                        void *ws, int num_cu, int mode, hipStream_t stream) {
     SelectArgs a{};
     a.dist = D;
     a.rows = rows;
@@ -136,7 +172,7 @@ hipError_t select_dense(const float *D, int64_t rows, int64_t cols, int64_t ld, 
     a.k = (uint32_t)k;
     a.out_val = ov;
     a.out_idx = oi;
-    a.mode = kPivotSample;
+    a.mode = mode;
     int cap = select_cap_for_k((uint32_t)k);
     return launch_select(a, cap, select_grid(cap, rows, num_cu), ws, stream);
 }
@@ -146,6 +182,9 @@ hipError_t select_dense(const float *D, int64_t rows, int64_t cols, int64_t ld, 
 knn_status_t run_search(knn_handle_t h, const float *Q, int64_t m, const float *C, int64_t n, int d, int k, bool graph,
                         float *out_dist, int32_t *out_idx, hipStream_t stream, const knn_options_t *opt) {
     const int num_cu = handle_num_cu(h);
+    // pivot rule of every quick multi-select in the path (no pivot network yet:
+    // the learned rule uses the sample rule)
+    const int smode = (opt && opt->pivot == KNN_PIVOT_PLAIN) ? kPivotPlain : kPivotSample;
     Plan p{};
     p.m = m;
     p.n = n;
@@ -207,6 +246,8 @@ knn_status_t run_search(knn_handle_t h, const float *Q, int64_t m, const float *
 
     KNN_TRY(launch_sqnorm(C, n, d, b.cnorm, stream));
     int64_t fallback_total = 0;
+    ProductTimer timer;
+    KNN_TRY(timer.init(opt && (opt->flags & KNN_FLAG_TIMING)));
 
     if (p.unfused) {
         for (int64_t i0 = 0; i0 < m; i0 += p.Mu) {
@@ -221,10 +262,16 @@ knn_status_t run_search(knn_handle_t h, const float *Q, int64_t m, const float *
             a.self_offset = graph ? i0 : -1;
             a.out = b.Dm;
             a.ldo = n;
+            KNN_TRY(timer.begin(stream, 2.0 * (double)mb * (double)n * d));
             KNN_TRY(launch_dist_gemm(a, kEpiDense, stream));
-            KNN_TRY(select_dense(b.Dm, mb, n, n, p.kk, b.sv, b.si, b.selws, num_cu, stream));
+            KNN_TRY(timer.end(stream));
+            KNN_TRY(select_dense(b.Dm, mb, n, n, p.kk, b.sv, b.si, b.selws, num_cu, smode, stream));
             RerankArgs rr{Q + i0 * d, mb, C, n, d, b.si, (uint32_t)p.kk, k, out_dist + i0 * k, out_idx + i0 * k};
             KNN_TRY(launch_rerank(rr, stream));
+            if (timer.on) {
+                KNN_TRY(hipStreamSynchronize(stream));
+                KNN_TRY(timer.collect(h));
+            }
         }
         add_host_stats(h, m, 0);
         return KNN_SUCCESS;
@@ -252,7 +299,7 @@ knn_status_t run_search(knn_handle_t h, const float *Q, int64_t m, const float *
         sa.out = b.Ds;
         sa.ldo = p.S;
         KNN_TRY(launch_dist_gemm(sa, kEpiDense, stream));
-        KNN_TRY(select_dense(b.Ds, mb, p.S, p.S, p.r + 1, b.tv, b.ti, b.selws, num_cu, stream));
+        KNN_TRY(select_dense(b.Ds, mb, p.S, p.S, p.r + 1, b.tv, b.ti, b.selws, num_cu, smode, stream));
         // 2. fused product + filter
         KNN_TRY(launch_fill_u32(b.cnt, mb, 0u, stream));
         DistArgs fa{};
@@ -268,13 +315,16 @@ knn_status_t run_search(knn_handle_t h, const float *Q, int64_t m, const float *
         fa.cnt = b.cnt;
         fa.cand = b.cand;
         fa.cap = p.cap;
+        KNN_TRY(timer.begin(stream, 2.0 * (double)mb * (double)n * d));
         KNN_TRY(launch_dist_gemm(fa, kEpiFilter, stream));
+        KNN_TRY(timer.end(stream));
         KNN_TRY(launch_sum_u32(b.cnt, mb, stats_ptr(h) + kStatCandidates, stream));
         // 3. exact re-do of rows whose candidate list is unusable
         KNN_TRY(launch_fill_u32(b.nflag, 1, 0u, stream));
         KNN_TRY(launch_flag_rows(b.cnt, mb, (uint32_t)p.kk, (uint32_t)p.cap, p.force, b.nflag, b.flags, stream));
         KNN_TRY(hipMemcpyAsync(hcount, b.nflag, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
         KNN_TRY(hipStreamSynchronize(stream));
+        KNN_TRY(timer.collect(h));
         const int64_t nf = *hcount;
         fallback_total += nf;
         for (int64_t f0 = 0; f0 < nf; f0 += p.Fb) {
@@ -292,7 +342,7 @@ knn_status_t run_search(knn_handle_t h, const float *Q, int64_t m, const float *
             da.out = b.Df;
             da.ldo = n;
             KNN_TRY(launch_dist_gemm(da, kEpiDense, stream));
-            KNN_TRY(select_dense(b.Df, fb, n, n, p.kk, b.fv, b.fi, b.selws, num_cu, stream));
+            KNN_TRY(select_dense(b.Df, fb, n, n, p.kk, b.fv, b.fi, b.selws, num_cu, smode, stream));
             KNN_TRY(launch_scatter_fallback(b.flags + f0, fb, b.fv, b.fi, p.kk, b.cand, b.cnt, p.cap, stream));
         }
         // 4. kk smallest candidates, exact re-rank, final k
@@ -305,7 +355,7 @@ knn_status_t run_search(knn_handle_t h, const float *Q, int64_t m, const float *
         ka.k = (uint32_t)p.kk;
         ka.out_val = b.sv;
         ka.out_idx = b.si;
-        ka.mode = kPivotSample;
+        ka.mode = smode;
         KNN_TRY(launch_select_keys(ka, mb, num_cu, stream));
         RerankArgs rr{Qb, mb, C, n, d, b.si, (uint32_t)p.kk, k, out_dist + i0 * k, out_idx + i0 * k};
         KNN_TRY(launch_rerank(rr, stream));
