@@ -64,10 +64,15 @@ typedef enum {
     KNN_PIVOT_LEARNED = 2
 } knn_pivot_t;
 
+/* Operand precision of the distance product in knn_search / knn_graph.  The
+ * candidates it ranks are always re-ranked with exact FP32 distances. */
 typedef enum {
-    KNN_PREC_FP32 = 0,      /* FP32 inputs on the FP32 matrix cores             */
-    KNN_PREC_BF16 = 1,      /* BF16 (round to nearest even) inputs, FP32 accum.  */
-    KNN_PREC_FP8_E4M3 = 2   /* OCP e4m3 with a power-of-two scale per point       */
+    KNN_PREC_FP32 = 0,      /* FP32 inputs on the FP32 matrix cores                */
+    KNN_PREC_BF16 = 1,      /* BF16 (round to nearest even) inputs, FP32 accumulation */
+    KNN_PREC_FP8_E4M3 = 2   /* OCP e4m3 (round to nearest even, saturating) after a   */
+                            /* per-point power-of-two scale 2^e, e the largest with   */
+                            /* max|x| 2^e <= 448; FP32 accumulation, scales undone    */
+                            /* exactly in the epilogue                                */
 } knn_precision_t;
 
 typedef struct {
@@ -102,6 +107,8 @@ typedef struct {
     int64_t product_launches;     /* distance-product launches (fused or dense),   */
     double product_flops;         /* their count, and their algorithmic flops      */
                                   /* (2 * rows * cols * d each)                    */
+    int64_t rows_uncertified;     /* search / graph rows whose candidate margin    */
+                                  /* does not exceed twice the key error bound     */
 } knn_stats_t;
 
 /* Create a handle bound to HIP device `device` (must be gfx950). */
@@ -167,8 +174,8 @@ knn_status_t knn_partition(knn_handle_t h, const float *in, int64_t rows, int64_
  *   k         1 <= k <= min(n, 1024)
  *   out_dist  m x k FP32 squared distances                          [out]
  *   out_idx   m x k int32 corpus indices                            [out]
- * Errors: INVALID_VALUE for null pointers, m < 0, n < 1, d < 1, k < 1, k > n;
- * UNSUPPORTED for k > 1024, n > INT32_MAX or an unsupported precision.
+ * Errors: INVALID_VALUE for null pointers, m < 0, n < 1, d < 1, k < 1, k > n,
+ * a bad option; UNSUPPORTED for k > 1024 or n > INT32_MAX.
  */
 knn_status_t knn_search(knn_handle_t h, const float *queries, int64_t m, const float *corpus,
                         int64_t n, int32_t d, int32_t k, float *out_dist, int32_t *out_idx,
@@ -203,6 +210,63 @@ knn_status_t knn_graph(knn_handle_t h, const float *points, int64_t n, int32_t d
  */
 knn_status_t knn_distances(knn_handle_t h, const float *queries, int64_t m, const float *corpus,
                            int64_t n, int32_t d, float *out, int64_t ldo, void *stream);
+
+/*
+ * Pivot network (learned first pivot of the quick multi-select).
+ *
+ * The paper leaves the pivot rule of its method open (Methods, "GPU-based quick
+ * multi-select": only the cited quicksort's random pivot is described).  This
+ * network predicts, from statistics of a 256-entry strided sample of a row
+ * (4 blocks of 64 contiguous entries), the standardised value of the row's
+ * k-th smallest entry, y = (v_k - m) / s (m: sample lower median, s: sample
+ * interquartile range / 1.349), so that the first partition pass keeps just
+ * over k keys.  8 features -> 64 -> 64 -> 1, ReLU, BF16 weights with FP32
+ * accumulation; trained with a pinball (quantile) loss by the kernels below.
+ * Features, in order: log2(N)/16, log2(k)/10, and (v - m)/s for the sample
+ * minimum, the sample entries at ranks r and r+1 with r = ceil(256 k / N) - 1,
+ * the entry at rank 25 and the sample mean, then log(s / (|m| + s)).
+ * Parameter layout (KNN_PIVOT_NPARAM floats): W1 (64 x 8, row-major), b1 (64),
+ * W2 (64 x 64), b2 (64), w3 (64), b3.
+ * When no network is loaded, KNN_PIVOT_LEARNED behaves as KNN_PIVOT_SAMPLE; an
+ * unusable prediction (NaN, infinite) falls back to the sample rule per row.
+ */
+#define KNN_PIVOT_NPARAM 4801
+
+/* FP32 master weights from a host array of KNN_PIVOT_NPARAM finite floats;
+ * resets the optimiser state.  Synchronous. */
+knn_status_t knn_pivot_set_weights(knn_handle_t h, const float *host_params, int32_t n);
+/* FP32 master weights into a host array.  Synchronises the device. */
+knn_status_t knn_pivot_get_weights(knn_handle_t h, float *host_params, int32_t n);
+/* Writes / reads a weights file: "KNNPIV01", version, sizes, optimiser step,
+ * training quantile, FP32 master weights.  IO on failure. */
+knn_status_t knn_pivot_save(knn_handle_t h, const char *path);
+knn_status_t knn_pivot_load(knn_handle_t h, const char *path);
+/*
+ * The 8 features of every row of a distance matrix for a given k.
+ *   dist       rows x cols FP32, row stride ld, cols >= 256          [in, device]
+ *   feats      rows x 8 FP32                                         [out, device]
+ *   loc_scale  rows x 2 FP32 (m, s), or NULL                         [out, device]
+ * Errors: INVALID_VALUE for bad sizes or null pointers; UNSUPPORTED for
+ * cols < 256 or cols > INT32_MAX.
+ */
+knn_status_t knn_pivot_features(knn_handle_t h, const float *dist, int64_t rows, int64_t cols,
+                                int64_t ld, int32_t k, float *feats, float *loc_scale, void *stream);
+/* Standardised predictions y_hat (rows) for feature rows (rows x 8), with the
+ * BF16 weights.  INVALID_VALUE if no network is loaded. */
+knn_status_t knn_pivot_predict(knn_handle_t h, const float *feats, int64_t rows, float *y_hat,
+                               void *stream);
+/*
+ * Mean pinball loss at `quantile` (0 < q < 1) of a batch and its gradient with
+ * respect to the (BF16-rounded) weights, FP32, summed over the batch in order.
+ *   feats (B x 8), targets (B), grad (KNN_PIVOT_NPARAM), loss (1)   [device]
+ */
+knn_status_t knn_pivot_grad(knn_handle_t h, const float *feats, const float *targets, int64_t B,
+                            float quantile, float *grad, float *loss, void *stream);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8, learning rate lr) on the FP32
+ * master weights with the gradient above; refreshes the BF16 copy.  loss may
+ * be NULL. */
+knn_status_t knn_pivot_train_step(knn_handle_t h, const float *feats, const float *targets,
+                                  int64_t B, float quantile, float lr, float *loss, void *stream);
 
 /* Counters of the last select / search / graph call on `h`.  Synchronises the
  * stream that call used. */

@@ -31,7 +31,9 @@ def _torch():
 class Handle:
     """Owns a libknn handle (device workspace, statistics) on one device."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, pivot_weights: str | None = "default"):
+        """pivot_weights: a weights file for the learned pivot, "default" for the
+        packaged one (if present), or None for none."""
         self.lib = _abi.load()
         h = ctypes.c_void_p()
         st = self.lib.knn_create(ctypes.byref(h), device)
@@ -39,6 +41,13 @@ class Handle:
             raise KnnError(st, self.lib.knn_last_error(None).decode())
         self.h = h
         self.device = device
+        if pivot_weights == "default":
+            import os
+            pivot_weights = os.path.join(os.path.dirname(os.path.abspath(__file__)), "pivot_weights.bin")
+            if not os.path.exists(pivot_weights):
+                pivot_weights = None
+        if pivot_weights:
+            self.pivot_load(pivot_weights)
 
     def close(self):
         if getattr(self, "h", None):
@@ -139,6 +148,62 @@ class Handle:
                                            ctypes.c_void_p(corpus.data_ptr()), n, d,
                                            ctypes.c_void_p(out.data_ptr()), n, self._stream()))
         return out
+
+    # ---- pivot network -------------------------------------------------------
+    def pivot_set_weights(self, params):
+        import numpy as np
+        w = np.ascontiguousarray(params, dtype=np.float32)
+        self._check(self.lib.knn_pivot_set_weights(self.h, w.ctypes.data_as(ctypes.c_void_p), w.size))
+
+    def pivot_get_weights(self):
+        import numpy as np
+        w = np.empty(_abi.PIVOT_NPARAM, np.float32)
+        self._check(self.lib.knn_pivot_get_weights(self.h, w.ctypes.data_as(ctypes.c_void_p), w.size))
+        return w
+
+    def pivot_save(self, path: str):
+        self._check(self.lib.knn_pivot_save(self.h, str(path).encode()))
+
+    def pivot_load(self, path: str):
+        self._check(self.lib.knn_pivot_load(self.h, str(path).encode()))
+
+    def pivot_features(self, dist, k: int):
+        """Features [rows, 8] and (m, s) [rows, 2] of each row of a device matrix."""
+        torch = _torch()
+        rows, cols = dist.shape
+        f = torch.empty((rows, 8), dtype=torch.float32, device=dist.device)
+        ms = torch.empty((rows, 2), dtype=torch.float32, device=dist.device)
+        self._check(self.lib.knn_pivot_features(self.h, ctypes.c_void_p(dist.data_ptr()), rows, cols,
+                                                max(dist.stride(0), cols), k, ctypes.c_void_p(f.data_ptr()),
+                                                ctypes.c_void_p(ms.data_ptr()), self._stream()))
+        return f, ms
+
+    def pivot_predict(self, feats):
+        torch = _torch()
+        feats = feats.contiguous()
+        out = torch.empty((feats.shape[0],), dtype=torch.float32, device=feats.device)
+        self._check(self.lib.knn_pivot_predict(self.h, ctypes.c_void_p(feats.data_ptr()), feats.shape[0],
+                                               ctypes.c_void_p(out.data_ptr()), self._stream()))
+        return out
+
+    def pivot_grad(self, feats, targets, quantile: float):
+        torch = _torch()
+        feats, targets = feats.contiguous(), targets.contiguous()
+        g = torch.empty((_abi.PIVOT_NPARAM,), dtype=torch.float32, device=feats.device)
+        loss = torch.empty((1,), dtype=torch.float32, device=feats.device)
+        self._check(self.lib.knn_pivot_grad(self.h, ctypes.c_void_p(feats.data_ptr()),
+                                            ctypes.c_void_p(targets.data_ptr()), feats.shape[0], quantile,
+                                            ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(loss.data_ptr()),
+                                            self._stream()))
+        return g, loss
+
+    def pivot_train_step(self, feats, targets, quantile: float, lr: float):
+        torch = _torch()
+        loss = torch.empty((1,), dtype=torch.float32, device=feats.device)
+        self._check(self.lib.knn_pivot_train_step(self.h, ctypes.c_void_p(feats.data_ptr()),
+                                                  ctypes.c_void_p(targets.data_ptr()), feats.shape[0], quantile,
+                                                  lr, ctypes.c_void_p(loss.data_ptr()), self._stream()))
+        return loss
 
     def graph(self, points, k: int, pivot="sample", precision="fp32", oversample=4, flags=0):
         """k-NN graph of the rows of `points` (own index excluded).

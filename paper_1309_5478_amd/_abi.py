@@ -18,6 +18,7 @@ PREC_FP32, PREC_BF16, PREC_FP8_E4M3 = 0, 1, 2
 FLAG_FORCE_FALLBACK = 0x1
 FLAG_UNFUSED = 0x2
 FLAG_TIMING = 0x4
+PIVOT_NPARAM = 4801
 
 
 class Options(ctypes.Structure):
@@ -32,7 +33,7 @@ class Stats(ctypes.Structure):
                 ("first_pass_survivors", ctypes.c_int64), ("fallback_rows", ctypes.c_int64),
                 ("candidates_total", ctypes.c_int64), ("phase_cycles", ctypes.c_int64 * 4),
                 ("product_ms", ctypes.c_double), ("product_launches", ctypes.c_int64),
-                ("product_flops", ctypes.c_double)]
+                ("product_flops", ctypes.c_double), ("rows_uncertified", ctypes.c_int64)]
 
     def as_dict(self):
         d = {name: int(getattr(self, name)) for name, _ in self._fields_
@@ -59,6 +60,14 @@ PROTOTYPES = {
     "knn_graph": (_ST, [_P, _P, _I64, _I32, _I32, _P, _P, _P, ctypes.POINTER(Options)]),
     "knn_distances": (_ST, [_P, _P, _I64, _P, _I64, _I32, _P, _I64, _P]),
     "knn_get_stats": (_ST, [_P, ctypes.POINTER(Stats)]),
+    "knn_pivot_set_weights": (_ST, [_P, _P, _I32]),
+    "knn_pivot_get_weights": (_ST, [_P, _P, _I32]),
+    "knn_pivot_save": (_ST, [_P, ctypes.c_char_p]),
+    "knn_pivot_load": (_ST, [_P, ctypes.c_char_p]),
+    "knn_pivot_features": (_ST, [_P, _P, _I64, _I64, _I64, _I32, _P, _P, _P]),
+    "knn_pivot_predict": (_ST, [_P, _P, _I64, _P, _P]),
+    "knn_pivot_grad": (_ST, [_P, _P, _P, _I64, ctypes.c_float, _P, _P, _P]),
+    "knn_pivot_train_step": (_ST, [_P, _P, _P, _I64, ctypes.c_float, ctypes.c_float, _P, _P]),
 }
 
 _lib = None

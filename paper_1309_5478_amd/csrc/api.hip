@@ -8,28 +8,11 @@
 #include <string>
 
 #include "dist.hpp"
+#include "handle.hpp"
 #include "internal.hpp"
 #include "knn.h"
 
 using namespace knn;
-
-struct knn_handle_s {
-    int device = 0;
-    int num_cu = 0;
-    std::string arch;
-    void *ws = nullptr;        // general workspace, grows on demand
-    size_t ws_bytes = 0;
-    unsigned long long *stats_dev = nullptr;  // kStatCount counters
-    hipStream_t last_stream = nullptr;
-    knn_stats_t last{};
-    bool stats_pending = false;
-    int64_t host_rows = 0, host_fallback = 0;  // host-side counters of the last call
-    double host_product_ms = 0, host_product_flops = 0;
-    int64_t host_product_launches = 0;
-    uint32_t *pinned = nullptr;                 // one pinned word for device-to-host counts
-    std::string err;
-    int grid_cache[3] = {0, 0, 0};  // blocks per CU per select capacity class
-};
 
 static thread_local std::string g_err;  // errors with no handle
 
@@ -51,6 +34,7 @@ knn_status_t fail_msg(knn_handle_t h, knn_status_t s, const std::string &msg) { 
 uint32_t *host_counter(knn_handle_t h) { return h->pinned; }
 unsigned long long *stats_ptr(knn_handle_t h) { return h->stats_dev; }
 int handle_num_cu(knn_handle_t h) { return h->num_cu; }
+const uint16_t *handle_net(knn_handle_t h) { return h->has_net ? h->net_bf16 : nullptr; }
 void add_host_stats(knn_handle_t h, int64_t rows, int64_t fallback_rows) {
     h->host_rows += rows;
     h->host_fallback += fallback_rows;
@@ -145,6 +129,9 @@ knn_status_t knn_destroy(knn_handle_t h) {
     if (h->ws) hipFree(h->ws);
     if (h->stats_dev) hipFree(h->stats_dev);
     if (h->pinned) hipHostFree(h->pinned);
+    for (void *p : {(void *)h->net_theta, (void *)h->net_theta_r, (void *)h->net_m, (void *)h->net_v,
+                    (void *)h->net_grad, (void *)h->net_bf16})
+        if (p) hipFree(p);
     delete h;
     return KNN_SUCCESS;
 }
@@ -178,7 +165,7 @@ knn_status_t knn_select_k(knn_handle_t h, const float *dist, int64_t rows, int64
     if (!dist || !out_val || !out_idx) return fail(h, KNN_ERROR_INVALID_VALUE, "knn_select_k: null pointer");
     hipStream_t stream = static_cast<hipStream_t>(stream_);
     hipSetDevice(h->device);
-    if (mode == kPivotLearned) mode = kPivotSample;  // no pivot network loaded: sample rule
+    if (mode == kPivotLearned && !h->has_net) mode = kPivotSample;  // no pivot network loaded: sample rule
     int cap = select_cap_for_k((uint32_t)k);
     int grid = select_grid(cap, rows, h->num_cu);
     void *ws = nullptr;
@@ -194,7 +181,7 @@ knn_status_t knn_select_k(knn_handle_t h, const float *dist, int64_t rows, int64
     a.k = (uint32_t)k;
     a.out_val = out_val;
     a.out_idx = out_idx;
-    a.pivot_hint = nullptr;
+    a.net = mode == kPivotLearned ? h->net_bf16 : nullptr;
     a.mode = mode;
     a.stats = h->stats_dev;
     hipError_t e = launch_select(a, cap, grid, ws, stream);
@@ -235,8 +222,6 @@ static knn_status_t check_options(knn_handle_t h, const char *fn, const knn_opti
     if (opt->oversample < 0) return fail(h, KNN_ERROR_INVALID_VALUE, std::string(fn) + ": oversample < 0");
     if (opt->precision < KNN_PREC_FP32 || opt->precision > KNN_PREC_FP8_E4M3)
         return fail(h, KNN_ERROR_INVALID_VALUE, std::string(fn) + ": bad precision");
-    if (opt->precision != KNN_PREC_FP32)
-        return fail(h, KNN_ERROR_UNSUPPORTED, std::string(fn) + ": only FP32 inputs are implemented");
     return KNN_SUCCESS;
 }
 
@@ -331,6 +316,7 @@ knn_status_t knn_get_stats(knn_handle_t h, knn_stats_t *out) {
         t.product_ms = h->host_product_ms;
         t.product_flops = h->host_product_flops;
         t.product_launches = h->host_product_launches;
+        t.rows_uncertified = (int64_t)s[kStatUncertified];
         t.candidates_total = (int64_t)s[kStatCandidates];
         t.phase_cycles[0] = (int64_t)s[kStatCycSample];
         t.phase_cycles[1] = (int64_t)s[kStatCycStream];

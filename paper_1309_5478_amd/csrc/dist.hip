@@ -32,7 +32,9 @@ struct GemmSmem {
     float tau[64 * WM];
     int64_t qid[64 * WM];  // global id of each query row (self exclusion), -1 if none
     float qn[64 * WM];
+    float qs[64 * WM];     // FP8 row scales 2^-e (1 otherwise)
     float cn[64 * WN];
+    float cs[64 * WN];     // -2 * column scale
 };
 
 // XCD-aware tile order: workgroups are dispatched round-robin over the eight
@@ -55,117 +57,78 @@ __device__ __forceinline__ void tile_of_block(uint32_t b, uint32_t tiles_m, uint
     tn = in / gsize;
 }
 
-template <int WM, int WN, bool VEC>
+// One 128-byte k-chunk per staged row: 32 FP32, 64 BF16 or 128 FP8 elements.
+// Each thread moves 16-byte pieces (row r = f / 8, piece c = f % 8).
+template <int WM, int WN, int PREC, bool VEC>
 __device__ __forceinline__ void load_chunk(const DistArgs &a, uint32_t row0, uint32_t col0, uint32_t kc, f32x4 *ra,
                                            f32x4 *rb) {
     constexpr int NT = 64 * WM * WN;
-    constexpr int A4 = 64 * WM * (kBK / 4) / NT;  // float4 loads per thread for A
-    constexpr int B4 = 64 * WN * (kBK / 4) / NT;
+    constexpr int A4 = 64 * WM * 8 / NT;  // 16-byte loads per thread for A
+    constexpr int B4 = 64 * WN * 8 / NT;
     const uint32_t tid = threadIdx.x;
 #pragma unroll
-    for (int x = 0; x < A4; ++x) {
-        uint32_t f = tid + NT * x, r = f / (kBK / 4), c = f % (kBK / 4);
-        uint32_t gi = row0 + r, k0 = kc * kBK + c * 4;
+    for (int x = 0; x < A4 + B4; ++x) {
+        const bool isA = x < A4;
+        const uint32_t f = tid + NT * (isA ? x : x - A4), r = f / 8, c = f % 8;
+        const uint32_t gi = (isA ? row0 : col0) + r;
+        const int64_t lim = isA ? a.m : a.n;
         f32x4 v = {0.f, 0.f, 0.f, 0.f};
-        if (gi < a.m) {
-            const float *p = a.Q + (int64_t)gi * a.d + k0;
-            if (VEC) {
-                if (k0 < (uint32_t)a.d) v = *reinterpret_cast<const f32x4 *>(p);
-            } else {
+        if ((int64_t)gi < lim) {
+            if (PREC == kPrecF32) {
+                const uint32_t k0 = kc * 32 + c * 4;
+                const float *p = (isA ? a.Q : a.C) + (int64_t)gi * a.d + k0;
+                if (VEC) {
+                    if (k0 < (uint32_t)a.d) v = *reinterpret_cast<const f32x4 *>(p);
+                } else {
 #pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    if (k0 + e < (uint32_t)a.d) v[e] = p[e];
+                    for (int e = 0; e < 4; ++e)
+                        if (k0 + e < (uint32_t)a.d) v[e] = p[e];
+                }
+            } else {
+                const char *p = static_cast<const char *>(isA ? a.Qq : a.Cq) + (int64_t)gi * a.ldq + kc * 128 + c * 16;
+                v = *reinterpret_cast<const f32x4 *>(p);
             }
         }
-        ra[x] = v;
-    }
-#pragma unroll
-    for (int x = 0; x < B4; ++x) {
-        uint32_t f = tid + NT * x, r = f / (kBK / 4), c = f % (kBK / 4);
-        uint32_t gj = col0 + r, k0 = kc * kBK + c * 4;
-        f32x4 v = {0.f, 0.f, 0.f, 0.f};
-        if (gj < a.n) {
-            const float *p = a.C + (int64_t)gj * a.d + k0;
-            if (VEC) {
-                if (k0 < (uint32_t)a.d) v = *reinterpret_cast<const f32x4 *>(p);
-            } else {
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    if (k0 + e < (uint32_t)a.d) v[e] = p[e];
-            }
-        }
-        rb[x] = v;
+        if (isA) ra[x] = v;
+        else rb[x - A4] = v;
     }
 }
 
 template <int WM, int WN>
 __device__ __forceinline__ void store_chunk(GemmSmem<WM, WN> &sm, int buf, const f32x4 *ra, const f32x4 *rb) {
     constexpr int NT = 64 * WM * WN;
-    constexpr int A4 = 64 * WM * (kBK / 4) / NT;
-    constexpr int B4 = 64 * WN * (kBK / 4) / NT;
+    constexpr int A4 = 64 * WM * 8 / NT;
+    constexpr int B4 = 64 * WN * 8 / NT;
     const uint32_t tid = threadIdx.x;
 #pragma unroll
     for (int x = 0; x < A4; ++x) {
-        uint32_t f = tid + NT * x, r = f / (kBK / 4), c = f % (kBK / 4);
+        uint32_t f = tid + NT * x, r = f / 8, c = f % 8;
         *reinterpret_cast<f32x4 *>(&sm.A[buf][r][c * 4]) = ra[x];
     }
 #pragma unroll
     for (int x = 0; x < B4; ++x) {
-        uint32_t f = tid + NT * x, r = f / (kBK / 4), c = f % (kBK / 4);
+        uint32_t f = tid + NT * x, r = f / 8, c = f % 8;
         *reinterpret_cast<f32x4 *>(&sm.B[buf][r][c * 4]) = rb[x];
     }
 }
 
-template <int WM, int WN, int EPI, bool VEC>
-__global__ __launch_bounds__(64 * WM * WN) void dist_gemm_kernel(DistArgs a) {
-    constexpr int NT = 64 * WM * WN;
-    constexpr int BM = 64 * WM, BN = 64 * WN;
-    constexpr int A4 = BM * (kBK / 4) / NT;
-    constexpr int B4 = BN * (kBK / 4) / NT;
-    static_assert(A4 >= 1 && B4 >= 1, "tile too small for the thread count");
-    __shared__ GemmSmem<WM, WN> sm;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
 
-    uint32_t tm, tn;
-    bool valid;
-    tile_of_block(blockIdx.x, a.tiles_m, a.tiles_n, tm, tn, valid);
-    if (!valid) return;  // whole workgroup leaves together
-    const uint32_t row0 = tm * BM, col0 = tn * BN;
-    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
-    const uint32_t wm = wave % WM, wn = wave / WM;
-    const uint32_t h = lane / 32, l32 = lane % 32;
-
-    // per-row thresholds and per-column norms for the epilogue
-    for (uint32_t t = tid; t < (uint32_t)BM; t += NT) {
-        uint32_t gi = row0 + t;
-        sm.tau[t] = (EPI == kEpiFilter && gi < a.m) ? a.tau[(int64_t)gi * a.tau_stride] : 0.f;
-        sm.qn[t] = (a.qnorm && gi < a.m) ? a.qnorm[gi] : 0.f;
-        sm.qid[t] = (a.self_offset >= 0 && gi < a.m) ? a.self_offset + (a.row_ids ? (int64_t)a.row_ids[gi] : (int64_t)gi)
-                                                     : (int64_t)-1;
-    }
-    for (uint32_t t = tid; t < (uint32_t)BN; t += NT) {
-        uint32_t gj = col0 + t;
-        sm.cn[t] = gj < a.n ? a.cnorm[gj] : 0.f;
-    }
-
-    f32x16 acc[2][2];
+// The MFMAs of one staged 128-byte chunk for a wave's 2 x 2 blocks of 32 x 32.
+//  FP32: 4 steps of 8 k; one 16-byte read per operand feeds 4 v_mfma_f32_32x32x2f32
+//        (lane half h holds k = 8s + 4h + q of MFMA q).
+//  BF16: 4 steps of 16 k; one 16-byte read per operand per v_mfma_f32_32x32x16_bf16
+//        (lane half h holds k = 16s + 8h .. +7).
+//  FP8:  2 steps of 64 k; two 16-byte reads per operand per
+//        v_mfma_scale_f32_32x32x64_f8f6f4 with OCP e4m3 operands and unit scales
+//        (lane half h holds k = 64s + 32h .. +31).
+template <int WM, int WN, int PREC>
+__device__ __forceinline__ void mma_chunk(GemmSmem<WM, WN> &sm, int cur, uint32_t wm, uint32_t wn, uint32_t h,
+                                          uint32_t l32, f32x16 (&acc)[2][2]) {
+    if (PREC == kPrecF32) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
-
-    const uint32_t nk = ((uint32_t)a.d + kBK - 1) / kBK;
-    f32x4 ra[A4], rb[B4];
-    load_chunk<WM, WN, VEC>(a, row0, col0, 0, ra, rb);
-    store_chunk<WM, WN>(sm, 0, ra, rb);
-    __syncthreads();
-
-    for (uint32_t kc = 0; kc < nk; ++kc) {
-        const int cur = kc & 1;
-        if (kc + 1 < nk) load_chunk<WM, WN, VEC>(a, row0, col0, kc + 1, ra, rb);
-#pragma unroll
-        for (int s = 0; s < kBK / 8; ++s) {
+        for (int s = 0; s < 4; ++s) {
             f32x4 fa[2], fb[2];
 #pragma unroll
             for (int i = 0; i < 2; ++i)
@@ -181,29 +144,124 @@ __global__ __launch_bounds__(64 * WM * WN) void dist_gemm_kernel(DistArgs a) {
                     for (int j = 0; j < 2; ++j)
                         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[i][q], fb[j][q], acc[i][j], 0, 0, 0);
         }
+    } else if (PREC == kPrecBF16) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            bf16x8 fa[2], fb[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+                fa[i] = *reinterpret_cast<const bf16x8 *>(
+                    reinterpret_cast<const char *>(&sm.A[cur][wm * 64 + i * 32 + l32][0]) + 32 * s + 16 * h);
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                fb[j] = *reinterpret_cast<const bf16x8 *>(
+                    reinterpret_cast<const char *>(&sm.B[cur][wn * 64 + j * 32 + l32][0]) + 32 * s + 16 * h);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            i32x8 fa[2], fb[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+                fa[i] = *reinterpret_cast<const i32x8 *>(
+                    reinterpret_cast<const char *>(&sm.A[cur][wm * 64 + i * 32 + l32][0]) + 64 * s + 32 * h);
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                fb[j] = *reinterpret_cast<const i32x8 *>(
+                    reinterpret_cast<const char *>(&sm.B[cur][wn * 64 + j * 32 + l32][0]) + 64 * s + 32 * h);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(fa[i], fb[j], acc[i][j], 0, 0, 0, 127,
+                                                                                0, 127);
+        }
+    }
+}
+
+template <int WM, int WN, int EPI, int PREC, bool VEC>
+__global__ __launch_bounds__(64 * WM * WN) void dist_gemm_kernel(DistArgs a) {
+    constexpr int NT = 64 * WM * WN;
+    constexpr int BM = 64 * WM, BN = 64 * WN;
+    constexpr int A4 = BM * 8 / NT;
+    constexpr int B4 = BN * 8 / NT;
+    static_assert(A4 >= 1 && B4 >= 1, "tile too small for the thread count");
+    __shared__ GemmSmem<WM, WN> sm;
+
+    uint32_t tm, tn;
+    bool valid;
+    tile_of_block(blockIdx.x, a.tiles_m, a.tiles_n, tm, tn, valid);
+    if (!valid) return;  // whole workgroup leaves together
+    const uint32_t row0 = tm * BM, col0 = tn * BN;
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    const uint32_t wm = wave % WM, wn = wave / WM;
+    const uint32_t h = lane / 32, l32 = lane % 32;
+
+    // per-row thresholds / ids / scales and per-column norms / scales for the epilogue
+    for (uint32_t t = tid; t < (uint32_t)BM; t += NT) {
+        uint32_t gi = row0 + t;
+        sm.tau[t] = (EPI == kEpiFilter && gi < a.m) ? a.tau[(int64_t)gi * a.tau_stride] : 0.f;
+        sm.qn[t] = (a.qnorm && gi < a.m) ? a.qnorm[gi] : 0.f;
+        sm.qs[t] = (PREC == kPrecFP8 && gi < a.m) ? a.qscale[gi] : 1.f;
+        sm.qid[t] = (a.self_offset >= 0 && gi < a.m) ? a.self_offset + (a.row_ids ? (int64_t)a.row_ids[gi] : (int64_t)gi)
+                                                     : (int64_t)-1;
+    }
+    for (uint32_t t = tid; t < (uint32_t)BN; t += NT) {
+        uint32_t gj = col0 + t;
+        sm.cn[t] = gj < a.n ? a.cnorm[gj] : 0.f;
+        sm.cs[t] = (PREC == kPrecFP8 && gj < a.n) ? -2.0f * a.cscale[gj] : -2.0f;
+    }
+
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    constexpr uint32_t per_chunk = PREC == kPrecF32 ? 32 : (PREC == kPrecBF16 ? 64 : 128);
+    const uint32_t nk = ((uint32_t)a.d + per_chunk - 1) / per_chunk;
+    f32x4 ra[A4], rb[B4];
+    load_chunk<WM, WN, PREC, VEC>(a, row0, col0, 0, ra, rb);
+    store_chunk<WM, WN>(sm, 0, ra, rb);
+    __syncthreads();
+
+    for (uint32_t kc = 0; kc < nk; ++kc) {
+        const int cur = kc & 1;
+        if (kc + 1 < nk) load_chunk<WM, WN, PREC, VEC>(a, row0, col0, kc + 1, ra, rb);
+        mma_chunk<WM, WN, PREC>(sm, cur, wm, wn, h, l32, acc);
         if (kc + 1 < nk) store_chunk<WM, WN>(sm, cur ^ 1, ra, rb);
         __syncthreads();
     }
 
     // epilogue: element (i, j) of block (bi, bj), register r, lane l:
     //   row = wm*64 + bi*32 + 8*(r/4) + 4*h + r%4, col = wn*64 + bj*32 + l%32
+    // d' = ||c_j||^2 - 2 q_i.c_j, with q_i.c_j = acc * qscale_i * cscale_j (FP8)
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) {
         const uint32_t cl = wn * 64 + bj * 32 + l32;
         const uint32_t gj = col0 + cl;
         const float cn = sm.cn[cl];
+        const float cs = sm.cs[cl];
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const uint32_t rl = wm * 64 + bi * 32 + 8 * (r / 4) + 4 * h + (r % 4);
                 const uint32_t gi = row0 + rl;
-                const float dp = fmaf(-2.0f, acc[bi][bj][r], cn);
+                const float dot = PREC == kPrecFP8 ? acc[bi][bj][r] * sm.qs[rl] : acc[bi][bj][r];
+                const float dp = fmaf(cs, dot, cn);
                 const bool in = (gi < a.m) & (gj < a.n);
                 const bool self = (int64_t)gj == sm.qid[rl];
                 if (EPI == kEpiDense) {
                     // with query norms: ||q||^2 + ||c||^2 - 2 q.c; without: the reduced key d'
-                    const float v = a.qnorm ? fmaf(-2.0f, acc[bi][bj][r], sm.qn[rl] + cn) : dp;
+                    const float v = a.qnorm ? fmaf(cs, dot, sm.qn[rl] + cn) : dp;
                     if (in) a.out[(int64_t)gi * a.ldo + gj] = self ? __uint_as_float(0x7f800000u) : v;
                 } else {
                     const bool pass = in & !self & (dp <= sm.tau[rl]);
@@ -343,6 +401,90 @@ __global__ __launch_bounds__(kRerankThreads) void rerank_kernel(RerankArgs a) {
     }
 }
 
+// ---- reduced-precision operands ---------------------------------------------
+// OCP e4m3 (1 sign, 4 exponent bits with bias 7, 3 mantissa bits, no infinity),
+// round to nearest even, saturating at +-448 (also for infinities).
+__device__ __forceinline__ uint8_t f32_to_e4m3(float x) {
+    const uint8_t sign = (uint8_t)((__float_as_uint(x) >> 24) & 0x80u);
+    const float a = fabsf(x);
+    if (!(a < 448.0f)) return sign | 0x7Eu;
+    if (a < 0.015625f) {                               // below 2^-6: subnormals, step 2^-9
+        return sign | (uint8_t)rintf(a * 512.0f);      // 8 (= 2^-6) encodes the smallest normal
+    }
+    int e = (int)((__float_as_uint(a) >> 23) & 0xFFu) - 127;  // floor(log2 a), in [-6, 8]
+    float r = rintf(ldexpf(a, 3 - e));                 // mantissa with the hidden bit, in [8, 16]
+    if (r >= 16.0f) {
+        r = 8.0f;
+        e += 1;
+    }
+    if (e > 8 || (e == 8 && r > 14.0f)) return sign | 0x7Eu;
+    return sign | (uint8_t)(((e + 7) << 3) | ((int)r - 8));
+}
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// One wave per point.  FP8: e = the largest integer with amax * 2^e <= 448
+// (0 for an all-zero point), elements x * 2^e rounded to e4m3, scale 2^-e.
+__global__ __launch_bounds__(256) void quantize_kernel(const float *__restrict__ X, int64_t n, int d, int prec, int dq,
+                                                       void *__restrict__ out, float *__restrict__ scale_out) {
+    const int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.x / kWave;
+    if (i >= n) return;
+    const uint32_t lane = lane_id();
+    const float *x = X + i * d;
+    if (prec == kPrecBF16) {
+        uint16_t *o = static_cast<uint16_t *>(out) + i * dq;
+        for (int t = lane; t < dq; t += kWave) o[t] = t < d ? f32_to_bf16_rne(x[t]) : (uint16_t)0;
+        return;
+    }
+    float amax = 0.f;
+    for (int t = lane; t < d; t += kWave) amax = fmaxf(amax, fabsf(x[t]));
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off));
+    int e = 0;
+    if (amax > 0.f && amax < 3.0e38f) {
+        e = (int)floorf(log2f(448.0f / amax));
+        while (ldexpf(amax, e + 1) <= 448.0f) ++e;
+        while (ldexpf(amax, e) > 448.0f) --e;
+        e = e < -100 ? -100 : (e > 100 ? 100 : e);
+    }
+    uint8_t *o = static_cast<uint8_t *>(out) + i * dq;
+    for (int t = lane; t < dq; t += kWave) o[t] = t < d ? f32_to_e4m3(ldexpf(x[t], e)) : (uint8_t)0;
+    if (lane == 0) scale_out[i] = ldexpf(1.0f, -e);
+}
+
+// Largest value of a non-negative array into *out (float bits compare as ints).
+__global__ __launch_bounds__(256) void max_nonneg_kernel(const float *__restrict__ x, int64_t n,
+                                                         unsigned int *__restrict__ out) {
+    float m = 0.f;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) m = fmaxf(m, x[i]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+    if (lane_id() == 0) atomicMax(out, __float_as_uint(m));
+}
+
+// A row's kk candidates are certified to contain its true k nearest when the
+// gap between the kk-th and the k-th candidate key exceeds twice the key error
+// bound E_i = 2 rel ||q_i|| max_j ||c_j|| (Cauchy-Schwarz on the dot-product
+// error).
+__global__ __launch_bounds__(256) void certify_kernel(const float *__restrict__ sk, int64_t m, int kk, int k,
+                                                      const float *__restrict__ qn2,
+                                                      const unsigned int *__restrict__ cmax2_bits, float rel,
+                                                      unsigned long long *__restrict__ count) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    bool bad = false;
+    if (i < m) {
+        const float gap = sk[i * kk + kk - 1] - sk[i * kk + k - 1];
+        const float E = 2.0f * rel * sqrtf(qn2[i]) * sqrtf(__uint_as_float(*cmax2_bits));
+        bad = !(gap > 2.0f * E);
+    }
+    const uint64_t b = __ballot(bad);
+    if (lane_id() == 0 && b) atomicAdd(count, (unsigned long long)__popcll(b));
+}
+
 // ---- host launchers ----------------------------------------------------------
 template <int WM, int WN, int EPI>
 static hipError_t launch_gemm_t(const DistArgs &a0, hipStream_t stream) {
@@ -353,10 +495,15 @@ static hipError_t launch_gemm_t(const DistArgs &a0, hipStream_t stream) {
     uint64_t T = (uint64_t)a.tiles_m * a.tiles_n;
     uint64_t grid = ((T + 7) / 8) * 8;
     if (grid > 0x7fffffffull) return hipErrorInvalidValue;
-    if (a.d % 4 == 0)
-        hipLaunchKernelGGL((dist_gemm_kernel<WM, WN, EPI, true>), dim3((unsigned)grid), dim3(64 * WM * WN), 0, stream, a);
+    const dim3 g((unsigned)grid), b(64 * WM * WN);
+    if (a.prec == kPrecBF16)
+        hipLaunchKernelGGL((dist_gemm_kernel<WM, WN, EPI, kPrecBF16, true>), g, b, 0, stream, a);
+    else if (a.prec == kPrecFP8)
+        hipLaunchKernelGGL((dist_gemm_kernel<WM, WN, EPI, kPrecFP8, true>), g, b, 0, stream, a);
+    else if (a.d % 4 == 0)
+        hipLaunchKernelGGL((dist_gemm_kernel<WM, WN, EPI, kPrecF32, true>), g, b, 0, stream, a);
     else
-        hipLaunchKernelGGL((dist_gemm_kernel<WM, WN, EPI, false>), dim3((unsigned)grid), dim3(64 * WM * WN), 0, stream, a);
+        hipLaunchKernelGGL((dist_gemm_kernel<WM, WN, EPI, kPrecF32, false>), g, b, 0, stream, a);
     return hipGetLastError();
 }
 
@@ -392,6 +539,31 @@ hipError_t launch_scatter_fallback(const int32_t *rows, int64_t nrows, const flo
     if (nrows == 0) return hipSuccess;
     hipLaunchKernelGGL(scatter_fallback_kernel, dim3((unsigned)nrows), dim3(256), 0, stream, rows, nrows, val, idx, kk,
                        cand, cnt, cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_quantize(const float *X, int64_t n, int d, int prec, void *out, float *scale_out,
+                           hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    const int dq = (d + kQuantPad - 1) / kQuantPad * kQuantPad;
+    hipLaunchKernelGGL(quantize_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, stream, X, n, d, prec, dq, out,
+                       scale_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_max_nonneg(const float *x, int64_t n, unsigned int *out, hipStream_t stream) {
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(max_nonneg_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, x, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_certify(const float *sorted_keys, int64_t m, int kk, int k, const float *qnorm2,
+                          const unsigned int *cmax2_bits, float rel, unsigned long long *count, hipStream_t stream) {
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(certify_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, stream, sorted_keys, m, kk, k,
+                       qnorm2, cmax2_bits, rel, count);
     return hipGetLastError();
 }
 

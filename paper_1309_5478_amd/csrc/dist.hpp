@@ -6,6 +6,11 @@
 namespace knn {
 
 enum : int { kEpiDense = 0, kEpiFilter = 1 };
+enum : int { kPrecF32 = 0, kPrecBF16 = 1, kPrecFP8 = 2 };
+
+// Quantised operands (BF16 / FP8): rows padded with zeros to a multiple of
+// kQuantPad elements, so every 128-byte k-chunk load is in bounds.
+constexpr int kQuantPad = 128;
 
 struct DistArgs {
     const float *Q;        // m x d queries
@@ -28,6 +33,15 @@ struct DistArgs {
     uint32_t *cnt;
     uint64_t *cand;
     int cap;
+    // operand precision; for BF16 / FP8 the product reads Qq / Cq (row stride
+    // ldq bytes) and, for FP8, undoes the per-row power-of-two scales
+    // qscale_i * cscale_j in the epilogue
+    int prec;
+    const void *Qq;
+    const void *Cq;
+    int64_t ldq;
+    const float *qscale;
+    const float *cscale;
     // filled by the launcher
     uint32_t tiles_m, tiles_n;
 };
@@ -54,5 +68,18 @@ hipError_t launch_flag_rows(const uint32_t *cnt, int64_t m, uint32_t need, uint3
 hipError_t launch_scatter_fallback(const int32_t *rows, int64_t nrows, const float *val, const int32_t *idx, int kk,
                                    uint64_t *cand, uint32_t *cnt, int cap, hipStream_t stream);
 hipError_t launch_rerank(const RerankArgs &a, hipStream_t stream);
+// Quantises n x d FP32 rows to BF16 (prec 1) or OCP e4m3 with a per-row
+// power-of-two scale (prec 2) into rows of dq = round_up(d, kQuantPad)
+// elements; scale_out (FP8 only) receives 2^-e per row.
+hipError_t launch_quantize(const float *X, int64_t n, int d, int prec, void *out, float *scale_out,
+                           hipStream_t stream);
+// Per-row certificate of a candidate list: the row is certified when the gap
+// between its kk-th and k-th candidate keys exceeds twice the bound on the key
+// error, 2 rel ||q_i|| max_j ||c_j||; uncertified rows are counted into *count.
+hipError_t launch_certify(const float *sorted_keys, int64_t m, int kk, int k, const float *qnorm2,
+                          const unsigned int *cmax2_bits, float rel, unsigned long long *count, hipStream_t stream);
+// Largest value of a non-negative FP32 array, as float bits, atomically into *out
+// (which must start at 0).
+hipError_t launch_max_nonneg(const float *x, int64_t n, unsigned int *out, hipStream_t stream);
 
 }  // namespace knn

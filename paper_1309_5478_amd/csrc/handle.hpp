@@ -1,0 +1,32 @@
+// The libknn handle (shared by the C ABI translation units).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "knn.h"
+
+struct knn_handle_s {
+    int device = 0;
+    int num_cu = 0;
+    std::string arch;
+    void *ws = nullptr;        // general workspace, grows on demand
+    size_t ws_bytes = 0;
+    unsigned long long *stats_dev = nullptr;  // kStatCount counters
+    hipStream_t last_stream = nullptr;
+    knn_stats_t last{};
+    bool stats_pending = false;
+    int64_t host_rows = 0, host_fallback = 0;  // host-side counters of the last call
+    double host_product_ms = 0, host_product_flops = 0;
+    int64_t host_product_launches = 0;
+    uint32_t *pinned = nullptr;                 // one pinned word for device-to-host counts
+    std::string err;
+    // pivot network: FP32 master weights, their BF16-rounded values (as FP32 for
+    // training, as BF16 for inference) and the Adam moments
+    float *net_theta = nullptr, *net_theta_r = nullptr, *net_m = nullptr, *net_v = nullptr, *net_grad = nullptr;
+    uint16_t *net_bf16 = nullptr;
+    int64_t net_step = 0;
+    bool has_net = false;
+    float net_quantile = 0.9f;
+};
+

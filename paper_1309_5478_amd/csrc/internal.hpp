@@ -22,7 +22,8 @@ enum StatSlot : int {
     kStatCycStream = 10,
     kStatCycSelect = 11,
     kStatCycFinal = 12,
-    kStatCount = 13
+    kStatUncertified = 13,
+    kStatCount = 14
 };
 
 // ---- selection over a given FP32 matrix ------------------------------------
@@ -34,7 +35,7 @@ struct SelectArgs {
     uint32_t k;
     float *out_val;        // rows x k
     int32_t *out_idx;      // rows x k
-    const float *pivot_hint;  // per-row first-pivot values (learned mode) or null
+    const uint16_t *net;   // pivot-network BF16 weights (learned mode), or null
     // key-list rows instead of `dist`: row r holds min(key_cnt[r], cols) keys at
     // keys + r * ld (cols must not exceed the kernel capacity)
     const uint64_t *keys;

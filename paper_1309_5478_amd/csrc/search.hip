@@ -34,6 +34,7 @@ unsigned long long *stats_ptr(knn_handle_t h);
 void add_host_stats(knn_handle_t h, int64_t rows, int64_t fallback_rows);
 void add_product_time(knn_handle_t h, double ms, double flops);
 int handle_num_cu(knn_handle_t h);
+const uint16_t *handle_net(knn_handle_t h);
 
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t stream);
 hipError_t launch_sum_u32(const uint32_t *p, int64_t n, unsigned long long *out, hipStream_t stream);
@@ -60,6 +61,9 @@ constexpr size_t kDenseBytes = size_t(1) << 30;  // materialised distance block 
 struct Plan {
     int64_t m, n, n_eff;
     int d, k, kk;
+    int prec;          // kPrecF32 / kPrecBF16 / kPrecFP8
+    int64_t ldq;       // bytes per quantised row
+    float rel;         // relative dot-product error bound of the precision
     bool graph, unfused;
     int force;
     // fused
@@ -75,6 +79,10 @@ struct Plan {
 
 struct Bufs {
     float *cnorm = nullptr;
+    float *qn2 = nullptr;
+    unsigned int *cmax2 = nullptr;
+    void *Cq = nullptr, *Qq = nullptr, *Csq = nullptr, *Qfq = nullptr;
+    float *cs = nullptr, *qs = nullptr, *css = nullptr, *qfs = nullptr;
     float *Cs = nullptr, *csn = nullptr;
     float *Ds = nullptr, *tv = nullptr;
     int32_t *ti = nullptr;
@@ -92,6 +100,22 @@ struct Bufs {
 
 size_t carve(Carve &c, const Plan &p, Bufs &b, int num_cu) {
     b.cnorm = c.take<float>(p.n);
+    b.qn2 = c.take<float>(p.m);
+    b.cmax2 = c.take<unsigned int>(1);
+    if (p.prec != kPrecF32) {
+        b.Cq = c.take<char>((size_t)p.n * p.ldq);
+        b.cs = c.take<float>(p.n);
+        if (!p.graph) {
+            b.Qq = c.take<char>((size_t)p.m * p.ldq);
+            b.qs = c.take<float>(p.m);
+        }
+        if (!p.unfused) {
+            b.Csq = c.take<char>((size_t)p.S * p.ldq);
+            b.css = c.take<float>(p.S);
+            b.Qfq = c.take<char>((size_t)p.Fb * p.ldq);
+            b.qfs = c.take<float>(p.Fb);
+        }
+    }
     size_t selws = 0;
     if (p.unfused) {
         b.Dm = c.take<float>((size_t)p.Mu * p.n);
@@ -163,7 +187,7 @@ struct ProductTimer {
 };
 
 hipError_t select_dense(const float *D, int64_t rows, int64_t cols, int64_t ld, int k, float *ov, int32_t *oi,
-                        void *ws, int num_cu, int mode, hipStream_t stream) {
+                        void *ws, int num_cu, int mode, const uint16_t *net, hipStream_t stream) {
     SelectArgs a{};
     a.dist = D;
     a.rows = rows;
@@ -173,6 +197,7 @@ hipError_t select_dense(const float *D, int64_t rows, int64_t cols, int64_t ld, 
     a.out_val = ov;
     a.out_idx = oi;
     a.mode = mode;
+    a.net = mode == kPivotLearned ? net : nullptr;
     int cap = select_cap_for_k((uint32_t)k);
     return launch_select(a, cap, select_grid(cap, rows, num_cu), ws, stream);
 }
@@ -182,9 +207,11 @@ hipError_t select_dense(const float *D, int64_t rows, int64_t cols, int64_t ld, 
 knn_status_t run_search(knn_handle_t h, const float *Q, int64_t m, const float *C, int64_t n, int d, int k, bool graph,
                         float *out_dist, int32_t *out_idx, hipStream_t stream, const knn_options_t *opt) {
     const int num_cu = handle_num_cu(h);
-    // pivot rule of every quick multi-select in the path (no pivot network yet:
-    // the learned rule uses the sample rule)
-    const int smode = (opt && opt->pivot == KNN_PIVOT_PLAIN) ? kPivotPlain : kPivotSample;
+    // pivot rule of every quick multi-select in the path (the learned rule needs
+    // a loaded pivot network; without one it is the sample rule)
+    const uint16_t *net = handle_net(h);
+    int smode = opt ? opt->pivot : kPivotSample;
+    if (smode == kPivotLearned && !net) smode = kPivotSample;
     Plan p{};
     p.m = m;
     p.n = n;
@@ -200,6 +227,14 @@ knn_status_t run_search(knn_handle_t h, const float *Q, int64_t m, const float *
     p.kk = (int)kk;
     p.unfused = opt && (opt->flags & KNN_FLAG_UNFUSED);
     p.force = (opt && (opt->flags & KNN_FLAG_FORCE_FALLBACK)) ? 1 : 0;
+    p.prec = opt ? opt->precision : KNN_PREC_FP32;
+    {
+        const int dq = (d + kQuantPad - 1) / kQuantPad * kQuantPad;
+        p.ldq = (int64_t)dq * (p.prec == kPrecBF16 ? 2 : 1);
+        const double gamma = d * std::ldexp(1.0, -24) / (1.0 - d * std::ldexp(1.0, -24));
+        const double u = p.prec == kPrecBF16 ? std::ldexp(1.0, -8) : (p.prec == kPrecFP8 ? std::ldexp(1.0, -4) : 0.0);
+        p.rel = (float)(2 * u + u * u + gamma);
+    }
 
     if (p.unfused) {
         int64_t mu = (int64_t)(kDenseBytes / sizeof(float) / (size_t)n);
@@ -245,6 +280,37 @@ knn_status_t run_search(knn_handle_t h, const float *Q, int64_t m, const float *
     } while (0)
 
     KNN_TRY(launch_sqnorm(C, n, d, b.cnorm, stream));
+    KNN_TRY(launch_sqnorm(Q, m, d, b.qn2, stream));
+    KNN_TRY(launch_fill_u32(b.cmax2, 1, 0u, stream));
+    KNN_TRY(launch_max_nonneg(b.cnorm, n, b.cmax2, stream));
+    const void *Qq = nullptr, *Cq = nullptr;
+    const float *qsc = nullptr, *csc = nullptr;
+    if (p.prec != kPrecF32) {
+        KNN_TRY(launch_quantize(C, n, d, p.prec, b.Cq, b.cs, stream));
+        Cq = b.Cq;
+        csc = b.cs;
+        if (graph) {
+            Qq = b.Cq;
+            qsc = b.cs;
+        } else {
+            KNN_TRY(launch_quantize(Q, m, d, p.prec, b.Qq, b.qs, stream));
+            Qq = b.Qq;
+            qsc = b.qs;
+        }
+    }
+    auto set_prec = [&](DistArgs &a, const void *qq, const float *qs, const void *cq, const float *cs) {
+        a.prec = p.prec;
+        a.Qq = qq;
+        a.Cq = cq;
+        a.ldq = p.ldq;
+        a.qscale = qs;
+        a.cscale = cs;
+    };
+    auto qrow = [&](int64_t i0) -> const void * {
+        return Qq ? static_cast<const char *>(Qq) + i0 * p.ldq : nullptr;
+    };
+    auto qsrow = [&](int64_t i0) -> const float * { return qsc ? qsc + i0 : nullptr; };
+    const bool certify = p.kk < p.n_eff;
     int64_t fallback_total = 0;
     ProductTimer timer;
     KNN_TRY(timer.init(opt && (opt->flags & KNN_FLAG_TIMING)));
@@ -262,10 +328,14 @@ knn_status_t run_search(knn_handle_t h, const float *Q, int64_t m, const float *
             a.self_offset = graph ? i0 : -1;
             a.out = b.Dm;
             a.ldo = n;
+            set_prec(a, qrow(i0), qsrow(i0), Cq, csc);
             KNN_TRY(timer.begin(stream, 2.0 * (double)mb * (double)n * d));
             KNN_TRY(launch_dist_gemm(a, kEpiDense, stream));
             KNN_TRY(timer.end(stream));
-            KNN_TRY(select_dense(b.Dm, mb, n, n, p.kk, b.sv, b.si, b.selws, num_cu, smode, stream));
+            KNN_TRY(select_dense(b.Dm, mb, n, n, p.kk, b.sv, b.si, b.selws, num_cu, smode, net, stream));
+            if (certify)
+                KNN_TRY(launch_certify(b.sv, mb, p.kk, k, b.qn2 + i0, b.cmax2, p.rel, stats_ptr(h) + kStatUncertified,
+                                       stream));
             RerankArgs rr{Q + i0 * d, mb, C, n, d, b.si, (uint32_t)p.kk, k, out_dist + i0 * k, out_idx + i0 * k};
             KNN_TRY(launch_rerank(rr, stream));
             if (timer.on) {
@@ -278,10 +348,17 @@ knn_status_t run_search(knn_handle_t h, const float *Q, int64_t m, const float *
     }
 
     const float *Cs = C, *csn = b.cnorm;
+    const void *Csq = Cq;
+    const float *css = csc;
     if (p.gathered) {
         KNN_TRY(launch_gather_rows(C, n, d, nullptr, p.S, b.Cs, b.cnorm, b.csn, stream));
         Cs = b.Cs;
         csn = b.csn;
+        if (p.prec != kPrecF32) {
+            KNN_TRY(launch_quantize(b.Cs, p.S, d, p.prec, b.Csq, b.css, stream));
+            Csq = b.Csq;
+            css = b.css;
+        }
     }
     uint32_t *hcount = host_counter(h);
     for (int64_t i0 = 0; i0 < m; i0 += p.Mb) {
@@ -298,8 +375,9 @@ knn_status_t run_search(knn_handle_t h, const float *Q, int64_t m, const float *
         sa.self_offset = (graph && !p.gathered) ? i0 : -1;
         sa.out = b.Ds;
         sa.ldo = p.S;
+        set_prec(sa, qrow(i0), qsrow(i0), Csq, css);
         KNN_TRY(launch_dist_gemm(sa, kEpiDense, stream));
-        KNN_TRY(select_dense(b.Ds, mb, p.S, p.S, p.r + 1, b.tv, b.ti, b.selws, num_cu, smode, stream));
+        KNN_TRY(select_dense(b.Ds, mb, p.S, p.S, p.r + 1, b.tv, b.ti, b.selws, num_cu, smode, net, stream));
         // 2. fused product + filter
         KNN_TRY(launch_fill_u32(b.cnt, mb, 0u, stream));
         DistArgs fa{};
@@ -315,6 +393,7 @@ knn_status_t run_search(knn_handle_t h, const float *Q, int64_t m, const float *
         fa.cnt = b.cnt;
         fa.cand = b.cand;
         fa.cap = p.cap;
+        set_prec(fa, qrow(i0), qsrow(i0), Cq, csc);
         KNN_TRY(timer.begin(stream, 2.0 * (double)mb * (double)n * d));
         KNN_TRY(launch_dist_gemm(fa, kEpiFilter, stream));
         KNN_TRY(timer.end(stream));
@@ -330,6 +409,7 @@ knn_status_t run_search(knn_handle_t h, const float *Q, int64_t m, const float *
         for (int64_t f0 = 0; f0 < nf; f0 += p.Fb) {
             const int64_t fb = nf - f0 < p.Fb ? nf - f0 : p.Fb;
             KNN_TRY(launch_gather_rows(Qb, mb, d, b.flags + f0, fb, b.Qf, nullptr, nullptr, stream));
+            if (p.prec != kPrecF32) KNN_TRY(launch_quantize(b.Qf, fb, d, p.prec, b.Qfq, b.qfs, stream));
             DistArgs da{};
             da.Q = b.Qf;
             da.m = fb;
@@ -341,8 +421,9 @@ knn_status_t run_search(knn_handle_t h, const float *Q, int64_t m, const float *
             da.row_ids = b.flags + f0;
             da.out = b.Df;
             da.ldo = n;
+            set_prec(da, b.Qfq, b.qfs, Cq, csc);
             KNN_TRY(launch_dist_gemm(da, kEpiDense, stream));
-            KNN_TRY(select_dense(b.Df, fb, n, n, p.kk, b.fv, b.fi, b.selws, num_cu, smode, stream));
+            KNN_TRY(select_dense(b.Df, fb, n, n, p.kk, b.fv, b.fi, b.selws, num_cu, smode, net, stream));
             KNN_TRY(launch_scatter_fallback(b.flags + f0, fb, b.fv, b.fi, p.kk, b.cand, b.cnt, p.cap, stream));
         }
         // 4. kk smallest candidates, exact re-rank, final k
@@ -357,6 +438,9 @@ knn_status_t run_search(knn_handle_t h, const float *Q, int64_t m, const float *
         ka.out_idx = b.si;
         ka.mode = smode;
         KNN_TRY(launch_select_keys(ka, mb, num_cu, stream));
+        if (certify)
+            KNN_TRY(launch_certify(b.sv, mb, p.kk, k, b.qn2 + i0, b.cmax2, p.rel, stats_ptr(h) + kStatUncertified,
+                                   stream));
         RerankArgs rr{Qb, mb, C, n, d, b.si, (uint32_t)p.kk, k, out_dist + i0 * k, out_idx + i0 * k};
         KNN_TRY(launch_rerank(rr, stream));
     }

@@ -31,6 +31,7 @@
 // global workspace, so overflowing rows stay exact.
 #include "internal.hpp"
 #include "keys.hpp"
+#include "pivot_net.hpp"
 
 namespace knn {
 
@@ -340,6 +341,7 @@ template <int CAP, bool KEYS>
 __global__ __launch_bounds__(kSelThreads) void select_rows_kernel(SelectArgs a, uint64_t *ws,
                                                                    uint64_t ws_slot) {
     __shared__ SelSmem<CAP> sm;
+    static_assert(sizeof(sm.buf) >= (size_t)(kNetParams + 1) * 2, "partition buffers must hold the pivot network");
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
     const uint32_t N = a.cols, k = a.k;
     GBuf gb{ws + (uint64_t)blockIdx.x * 2 * ws_slot, ws + (uint64_t)blockIdx.x * 2 * ws_slot + ws_slot};
@@ -379,34 +381,50 @@ __global__ __launch_bounds__(kSelThreads) void select_rows_kernel(SelectArgs a, 
                 __syncthreads();
                 P = sm.pivot;
             } else {
-                load_sample_blocks(sm, row, N);
-                sample_loaded = true;
-                uint32_t rr0 = target_rank(kSortN, k, N, 3.0f, 3.0f);
-                if (rr0 < (uint32_t)kWave) {
-                    if (wave == 0) {
-                        uint64_t piv = merge_rank(sm, rr0);
-                        if (lane == 0) sm.pivot = piv;
+                bool from_net = false;
+                if (a.mode == kPivotLearned && a.net) {
+                    // learned: 4 sample blocks (one per wave) -> features -> network
+                    {
+                        const uint32_t j = net_sample_start(wave, N) + lane;
+                        sm.sortbuf[tid] = wave_sort64(make_key(row[j], j));
                     }
                     __syncthreads();
-                    P = sm.pivot;
-                } else {
-                    block_bitonic_sort<kSelThreads>(sm.sortbuf, kSortN);
-                    sample_sorted = true;
-                    P = sm.sortbuf[rr0];
+                    block_merge_runs<kSelThreads>(sm.sortbuf, kNetSample, kWave);
+                    float *vf = reinterpret_cast<float *>(sm.sortbuf + kNetSample);
+                    vf[tid] = ord_to_float(key_ord(sm.sortbuf[tid]));
+                    // the BF16 weights, staged in the (still unused) partition buffers
+                    uint32_t *wl = reinterpret_cast<uint32_t *>(&sm.buf[0][0]);
+                    const uint32_t *wg = reinterpret_cast<const uint32_t *>(a.net);
+                    for (uint32_t t = tid; t < (uint32_t)(kNetParams + 1) / 2; t += kSelThreads) wl[t] = wg[t];
+                    __syncthreads();
+                    if (wave == 0) {
+                        float x[kNetIn], m, s;
+                        net_features(vf, N, k, x, m, s);
+                        const float y = net_forward_wave(reinterpret_cast<const uint16_t *>(wl), x);
+                        if (lane == 0) sm.pivot = (uint64_t)__float_as_uint(fmaf(s, y, m));
+                    }
+                    __syncthreads();
+                    const float pv = __uint_as_float((uint32_t)sm.pivot);
+                    if (pv == pv && fabsf(pv) <= 3.0e38f) {  // unusable predictions fall back to the sample rule
+                        P = (uint64_t)ord32(pv) << 32;
+                        from_net = true;
+                    }
                 }
-                if (a.mode == kPivotLearned && a.pivot_hint) {
-                    float hv = a.pivot_hint[r];
-                    // a usable hint is finite and above the smallest sampled key
-                    if (hv == hv && fabsf(hv) <= 3.0e38f) {
-                        uint64_t hk = ((uint64_t)ord32(hv) << 32);
-                        uint64_t smin = sm.sortbuf[0];
-                        if (!sample_sorted) {
-                            for (int b2 = 1; b2 < kSampleBlocks; ++b2) {
-                                uint64_t c = sm.sortbuf[b2 * kWave];
-                                smin = c < smin ? c : smin;
-                            }
+                if (!from_net) {
+                    load_sample_blocks(sm, row, N);
+                    sample_loaded = true;
+                    uint32_t rr0 = target_rank(kSortN, k, N, 3.0f, 3.0f);
+                    if (rr0 < (uint32_t)kWave) {
+                        if (wave == 0) {
+                            uint64_t piv = merge_rank(sm, rr0);
+                            if (lane == 0) sm.pivot = piv;
                         }
-                        if (hk > smin) P = hk;
+                        __syncthreads();
+                        P = sm.pivot;
+                    } else {
+                        block_bitonic_sort<kSelThreads>(sm.sortbuf, kSortN);
+                        sample_sorted = true;
+                        P = sm.sortbuf[rr0];
                     }
                 }
             }
