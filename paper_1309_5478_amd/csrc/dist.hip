@@ -15,6 +15,9 @@
 // Epilogues: DENSE writes d' (a materialised distance block); FILTER keeps only
 // d' <= tau_i and appends (d', j) keys to a per-row candidate list, one global
 // reservation per 32-lane half-row per MFMA register.
+#include <cstdlib>
+#include <cstring>
+
 #include "dist.hpp"
 #include "keys.hpp"
 
@@ -25,16 +28,25 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int kBK = 32;       // k-chunk
 constexpr int kLdsStride = 36;  // floats per staged row
 
-template <int WM, int WN>
+// A workgroup tile of BM x BN outputs: WM x WN waves, each wave BI x BJ MFMA
+// blocks of 32 x 32.
+template <int WM, int WN, int BI, int BJ>
+struct Tile {
+    static constexpr int NT = 64 * WM * WN;
+    static constexpr int BM = 32 * BI * WM;
+    static constexpr int BN = 32 * BJ * WN;
+};
+
+template <int BM, int BN>
 struct GemmSmem {
-    float A[2][64 * WM][kLdsStride];
-    float B[2][64 * WN][kLdsStride];
-    float tau[64 * WM];
-    int64_t qid[64 * WM];  // global id of each query row (self exclusion), -1 if none
-    float qn[64 * WM];
-    float qs[64 * WM];     // FP8 row scales 2^-e (1 otherwise)
-    float cn[64 * WN];
-    float cs[64 * WN];     // -2 * column scale
+    float A[2][BM][kLdsStride];
+    float B[2][BN][kLdsStride];
+    float tau[BM];
+    int64_t qid[BM];  // global id of each query row (self exclusion), -1 if none
+    float qn[BM];
+    float qs[BM];     // FP8 row scales 2^-e (1 otherwise)
+    float cn[BN];
+    float cs[BN];     // -2 * column scale
 };
 
 // XCD-aware tile order: workgroups are dispatched round-robin over the eight
@@ -59,12 +71,11 @@ __device__ __forceinline__ void tile_of_block(uint32_t b, uint32_t tiles_m, uint
 
 // One 128-byte k-chunk per staged row: 32 FP32, 64 BF16 or 128 FP8 elements.
 // Each thread moves 16-byte pieces (row r = f / 8, piece c = f % 8).
-template <int WM, int WN, int PREC, bool VEC>
+template <int NT, int BM, int BN, int PREC, bool VEC>
 __device__ __forceinline__ void load_chunk(const DistArgs &a, uint32_t row0, uint32_t col0, uint32_t kc, f32x4 *ra,
                                            f32x4 *rb) {
-    constexpr int NT = 64 * WM * WN;
-    constexpr int A4 = 64 * WM * 8 / NT;  // 16-byte loads per thread for A
-    constexpr int B4 = 64 * WN * 8 / NT;
+    constexpr int A4 = BM * 8 / NT;  // 16-byte loads per thread for A
+    constexpr int B4 = BN * 8 / NT;
     const uint32_t tid = threadIdx.x;
 #pragma unroll
     for (int x = 0; x < A4 + B4; ++x) {
@@ -94,11 +105,10 @@ __device__ __forceinline__ void load_chunk(const DistArgs &a, uint32_t row0, uin
     }
 }
 
-template <int WM, int WN>
-__device__ __forceinline__ void store_chunk(GemmSmem<WM, WN> &sm, int buf, const f32x4 *ra, const f32x4 *rb) {
-    constexpr int NT = 64 * WM * WN;
-    constexpr int A4 = 64 * WM * 8 / NT;
-    constexpr int B4 = 64 * WN * 8 / NT;
+template <int NT, int BM, int BN>
+__device__ __forceinline__ void store_chunk(GemmSmem<BM, BN> &sm, int buf, const f32x4 *ra, const f32x4 *rb) {
+    constexpr int A4 = BM * 8 / NT;
+    constexpr int B4 = BN * 8 / NT;
     const uint32_t tid = threadIdx.x;
 #pragma unroll
     for (int x = 0; x < A4; ++x) {
@@ -123,75 +133,73 @@ typedef int i32x8 __attribute__((ext_vector_type(8)));
 //  FP8:  2 steps of 64 k; two 16-byte reads per operand per
 //        v_mfma_scale_f32_32x32x64_f8f6f4 with OCP e4m3 operands and unit scales
 //        (lane half h holds k = 64s + 32h .. +31).
-template <int WM, int WN, int PREC>
-__device__ __forceinline__ void mma_chunk(GemmSmem<WM, WN> &sm, int cur, uint32_t wm, uint32_t wn, uint32_t h,
-                                          uint32_t l32, f32x16 (&acc)[2][2]) {
+template <int BM, int BN, int BI, int BJ, int PREC>
+__device__ __forceinline__ void mma_chunk(GemmSmem<BM, BN> &sm, int cur, uint32_t r0, uint32_t c0, uint32_t h,
+                                          uint32_t l32, f32x16 (&acc)[BI][BJ]) {
     if (PREC == kPrecF32) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-            f32x4 fa[2], fb[2];
+            f32x4 fa[BI], fb[BJ];
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
-                fa[i] = *reinterpret_cast<const f32x4 *>(&sm.A[cur][wm * 64 + i * 32 + l32][8 * s + 4 * h]);
+            for (int i = 0; i < BI; ++i)
+                fa[i] = *reinterpret_cast<const f32x4 *>(&sm.A[cur][r0 + i * 32 + l32][8 * s + 4 * h]);
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
-                fb[j] = *reinterpret_cast<const f32x4 *>(&sm.B[cur][wn * 64 + j * 32 + l32][8 * s + 4 * h]);
+            for (int j = 0; j < BJ; ++j)
+                fb[j] = *reinterpret_cast<const f32x4 *>(&sm.B[cur][c0 + j * 32 + l32][8 * s + 4 * h]);
 #pragma unroll
             for (int q = 0; q < 4; ++q)
 #pragma unroll
-                for (int i = 0; i < 2; ++i)
+                for (int i = 0; i < BI; ++i)
 #pragma unroll
-                    for (int j = 0; j < 2; ++j)
+                    for (int j = 0; j < BJ; ++j)
                         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[i][q], fb[j][q], acc[i][j], 0, 0, 0);
         }
     } else if (PREC == kPrecBF16) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-            bf16x8 fa[2], fb[2];
+            bf16x8 fb[BJ];
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
-                fa[i] = *reinterpret_cast<const bf16x8 *>(
-                    reinterpret_cast<const char *>(&sm.A[cur][wm * 64 + i * 32 + l32][0]) + 32 * s + 16 * h);
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
+            for (int j = 0; j < BJ; ++j)
                 fb[j] = *reinterpret_cast<const bf16x8 *>(
-                    reinterpret_cast<const char *>(&sm.B[cur][wn * 64 + j * 32 + l32][0]) + 32 * s + 16 * h);
+                    reinterpret_cast<const char *>(&sm.B[cur][c0 + j * 32 + l32][0]) + 32 * s + 16 * h);
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < BI; ++i) {
+                const bf16x8 fa = *reinterpret_cast<const bf16x8 *>(
+                    reinterpret_cast<const char *>(&sm.A[cur][r0 + i * 32 + l32][0]) + 32 * s + 16 * h);
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+                for (int j = 0; j < BJ; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa, fb[j], acc[i][j], 0, 0, 0);
+            }
         }
     } else {
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
-            i32x8 fa[2], fb[2];
+            i32x8 fb[BJ];
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
-                fa[i] = *reinterpret_cast<const i32x8 *>(
-                    reinterpret_cast<const char *>(&sm.A[cur][wm * 64 + i * 32 + l32][0]) + 64 * s + 32 * h);
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
+            for (int j = 0; j < BJ; ++j)
                 fb[j] = *reinterpret_cast<const i32x8 *>(
-                    reinterpret_cast<const char *>(&sm.B[cur][wn * 64 + j * 32 + l32][0]) + 64 * s + 32 * h);
+                    reinterpret_cast<const char *>(&sm.B[cur][c0 + j * 32 + l32][0]) + 64 * s + 32 * h);
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < BI; ++i) {
+                const i32x8 fa = *reinterpret_cast<const i32x8 *>(
+                    reinterpret_cast<const char *>(&sm.A[cur][r0 + i * 32 + l32][0]) + 64 * s + 32 * h);
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(fa[i], fb[j], acc[i][j], 0, 0, 0, 127,
-                                                                                0, 127);
+                for (int j = 0; j < BJ; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(fa, fb[j], acc[i][j], 0, 0, 0, 127, 0,
+                                                                                127);
+            }
         }
     }
 }
 
-template <int WM, int WN, int EPI, int PREC, bool VEC>
+template <int WM, int WN, int BI, int BJ, int EPI, int PREC, bool VEC>
 __global__ __launch_bounds__(64 * WM * WN) void dist_gemm_kernel(DistArgs a) {
-    constexpr int NT = 64 * WM * WN;
-    constexpr int BM = 64 * WM, BN = 64 * WN;
+    using T = Tile<WM, WN, BI, BJ>;
+    constexpr int NT = T::NT, BM = T::BM, BN = T::BN;
     constexpr int A4 = BM * 8 / NT;
     constexpr int B4 = BN * 8 / NT;
-    static_assert(A4 >= 1 && B4 >= 1, "tile too small for the thread count");
-    __shared__ GemmSmem<WM, WN> sm;
+    static_assert(A4 >= 1 && B4 >= 1 && A4 * NT == BM * 8 && B4 * NT == BN * 8, "tile / thread mismatch");
+    __shared__ GemmSmem<BM, BN> sm;
 
     uint32_t tm, tn;
     bool valid;
@@ -200,6 +208,7 @@ __global__ __launch_bounds__(64 * WM * WN) void dist_gemm_kernel(DistArgs a) {
     const uint32_t row0 = tm * BM, col0 = tn * BN;
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
     const uint32_t wm = wave % WM, wn = wave / WM;
+    const uint32_t r0 = wm * 32 * BI, c0 = wn * 32 * BJ;  // wave origin in the tile
     const uint32_t h = lane / 32, l32 = lane % 32;
 
     // per-row thresholds / ids / scales and per-column norms / scales for the epilogue
@@ -217,54 +226,61 @@ __global__ __launch_bounds__(64 * WM * WN) void dist_gemm_kernel(DistArgs a) {
         sm.cs[t] = (PREC == kPrecFP8 && gj < a.n) ? -2.0f * a.cscale[gj] : -2.0f;
     }
 
-    f32x16 acc[2][2];
+    f32x16 acc[BI][BJ];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < BI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < BJ; ++j)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
     constexpr uint32_t per_chunk = PREC == kPrecF32 ? 32 : (PREC == kPrecBF16 ? 64 : 128);
     const uint32_t nk = ((uint32_t)a.d + per_chunk - 1) / per_chunk;
     f32x4 ra[A4], rb[B4];
-    load_chunk<WM, WN, PREC, VEC>(a, row0, col0, 0, ra, rb);
-    store_chunk<WM, WN>(sm, 0, ra, rb);
+    load_chunk<NT, BM, BN, PREC, VEC>(a, row0, col0, 0, ra, rb);
+    store_chunk<NT, BM, BN>(sm, 0, ra, rb);
     __syncthreads();
 
     for (uint32_t kc = 0; kc < nk; ++kc) {
         const int cur = kc & 1;
-        if (kc + 1 < nk) load_chunk<WM, WN, PREC, VEC>(a, row0, col0, kc + 1, ra, rb);
-        mma_chunk<WM, WN, PREC>(sm, cur, wm, wn, h, l32, acc);
-        if (kc + 1 < nk) store_chunk<WM, WN>(sm, cur ^ 1, ra, rb);
+        if (kc + 1 < nk) load_chunk<NT, BM, BN, PREC, VEC>(a, row0, col0, kc + 1, ra, rb);
+        mma_chunk<BM, BN, BI, BJ, PREC>(sm, cur, r0, c0, h, l32, acc);
+        if (kc + 1 < nk) store_chunk<NT, BM, BN>(sm, cur ^ 1, ra, rb);
         __syncthreads();
     }
 
     // epilogue: element (i, j) of block (bi, bj), register r, lane l:
-    //   row = wm*64 + bi*32 + 8*(r/4) + 4*h + r%4, col = wn*64 + bj*32 + l%32
-    // d' = ||c_j||^2 - 2 q_i.c_j, with q_i.c_j = acc * qscale_i * cscale_j (FP8)
+    //   row = r0 + bi*32 + 8*(r/4) + 4*h + r%4, col = c0 + bj*32 + l%32
+    // d' = ||c_j||^2 - 2 q_i.c_j, with q_i.c_j = acc * qscale_i * cscale_j (FP8).
+    // Interior tiles with no possible own-index column skip the per-element
+    // bounds and self tests.
+    const bool interior = row0 + BM <= a.m && col0 + BN <= a.n;
+    const bool may_self = a.self_offset >= 0;
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj) {
-        const uint32_t cl = wn * 64 + bj * 32 + l32;
-        const uint32_t gj = col0 + cl;
-        const float cn = sm.cn[cl];
-        const float cs = sm.cs[cl];
+    for (int bi = 0; bi < BI; ++bi) {
 #pragma unroll
-        for (int bi = 0; bi < 2; ++bi) {
+        for (int r = 0; r < 16; ++r) {
+            const uint32_t rl = r0 + bi * 32 + 8 * (r / 4) + 4 * h + (r % 4);
+            const uint32_t gi = row0 + rl;
+            const float tau = EPI == kEpiFilter ? sm.tau[rl] : 0.f;
+            const int64_t qid = sm.qid[rl];
+            const float qs = PREC == kPrecFP8 ? sm.qs[rl] : 1.f;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const uint32_t rl = wm * 64 + bi * 32 + 8 * (r / 4) + 4 * h + (r % 4);
-                const uint32_t gi = row0 + rl;
-                const float dot = PREC == kPrecFP8 ? acc[bi][bj][r] * sm.qs[rl] : acc[bi][bj][r];
+            for (int bj = 0; bj < BJ; ++bj) {
+                const uint32_t cl = c0 + bj * 32 + l32;
+                const uint32_t gj = col0 + cl;
+                const float cn = sm.cn[cl];
+                const float cs = sm.cs[cl];
+                const float dot = PREC == kPrecFP8 ? acc[bi][bj][r] * qs : acc[bi][bj][r];
                 const float dp = fmaf(cs, dot, cn);
-                const bool in = (gi < a.m) & (gj < a.n);
-                const bool self = (int64_t)gj == sm.qid[rl];
+                const bool in = interior || ((gi < a.m) & (gj < a.n));
+                const bool self = may_self && (int64_t)gj == qid;
                 if (EPI == kEpiDense) {
                     // with query norms: ||q||^2 + ||c||^2 - 2 q.c; without: the reduced key d'
                     const float v = a.qnorm ? fmaf(cs, dot, sm.qn[rl] + cn) : dp;
                     if (in) a.out[(int64_t)gi * a.ldo + gj] = self ? __uint_as_float(0x7f800000u) : v;
                 } else {
-                    const bool pass = in & !self & (dp <= sm.tau[rl]);
+                    const bool pass = in & !self & (dp <= tau);
                     const uint64_t m = __ballot(pass);
                     if (m) {
                         const uint32_t half = h ? (uint32_t)(m >> 32) : (uint32_t)m;
@@ -486,30 +502,60 @@ __global__ __launch_bounds__(256) void certify_kernel(const float *__restrict__ 
 }
 
 // ---- host launchers ----------------------------------------------------------
-template <int WM, int WN, int EPI>
+template <int WM, int WN, int BI, int BJ, int EPI>
 static hipError_t launch_gemm_t(const DistArgs &a0, hipStream_t stream) {
+    using T = Tile<WM, WN, BI, BJ>;
     DistArgs a = a0;
-    constexpr int BM = 64 * WM, BN = 64 * WN;
-    a.tiles_m = (uint32_t)((a.m + BM - 1) / BM);
-    a.tiles_n = (uint32_t)((a.n + BN - 1) / BN);
-    uint64_t T = (uint64_t)a.tiles_m * a.tiles_n;
-    uint64_t grid = ((T + 7) / 8) * 8;
+    a.tiles_m = (uint32_t)((a.m + T::BM - 1) / T::BM);
+    a.tiles_n = (uint32_t)((a.n + T::BN - 1) / T::BN);
+    uint64_t tiles = (uint64_t)a.tiles_m * a.tiles_n;
+    uint64_t grid = ((tiles + 7) / 8) * 8;
     if (grid > 0x7fffffffull) return hipErrorInvalidValue;
-    const dim3 g((unsigned)grid), b(64 * WM * WN);
-    if (a.prec == kPrecBF16)
-        hipLaunchKernelGGL((dist_gemm_kernel<WM, WN, EPI, kPrecBF16, true>), g, b, 0, stream, a);
-    else if (a.prec == kPrecFP8)
-        hipLaunchKernelGGL((dist_gemm_kernel<WM, WN, EPI, kPrecFP8, true>), g, b, 0, stream, a);
+    const dim3 g((unsigned)grid), b(T::NT);
+    if (a.prec == kPrecBF16) {
+        hipLaunchKernelGGL((dist_gemm_kernel<WM, WN, BI, BJ, EPI, kPrecBF16, true>), g, b, 0, stream, a);
+    } else if (a.prec == kPrecFP8) {
+        if constexpr (BI * BJ <= 4)
+            hipLaunchKernelGGL((dist_gemm_kernel<WM, WN, BI, BJ, EPI, kPrecFP8, true>), g, b, 0, stream, a);
+        else
+            return hipErrorInvalidValue;
+    }
     else if (a.d % 4 == 0)
-        hipLaunchKernelGGL((dist_gemm_kernel<WM, WN, EPI, kPrecF32, true>), g, b, 0, stream, a);
+        hipLaunchKernelGGL((dist_gemm_kernel<WM, WN, BI, BJ, EPI, kPrecF32, true>), g, b, 0, stream, a);
     else
-        hipLaunchKernelGGL((dist_gemm_kernel<WM, WN, EPI, kPrecF32, false>), g, b, 0, stream, a);
+        hipLaunchKernelGGL((dist_gemm_kernel<WM, WN, BI, BJ, EPI, kPrecF32, false>), g, b, 0, stream, a);
     return hipGetLastError();
+}
+
+// Tile shapes: small 128 x 128 (4 waves of 64 x 64), wide 128 x 256 (8 waves of
+// 64 x 64), big 256 x 256 (8 waves of 128 x 64; FP32 and BF16 only, its FP8
+// variant exceeds the register file).  Default: big for products that fill the
+// device with such tiles (wide for FP8), small otherwise.  KNN_GEMM_TILE
+// (small / wide / big) overrides the default where the shape is legal.
+int gemm_tile_choice(const DistArgs &a) {
+    const bool large = a.m >= 2048 && a.n >= 2048;
+    int t = large ? (a.prec == kPrecFP8 ? kTileWide : kTileBig) : kTileSmall;
+    if (const char *e = std::getenv("KNN_GEMM_TILE")) {
+        if (!std::strcmp(e, "small")) t = kTileSmall;
+        else if (!std::strcmp(e, "wide")) t = kTileWide;
+        else if (!std::strcmp(e, "big") && a.prec != kPrecFP8) t = kTileBig;
+    }
+    return t;
 }
 
 hipError_t launch_dist_gemm(const DistArgs &a, int epi, hipStream_t stream) {
     if (a.m == 0 || a.n == 0) return hipSuccess;
-    return epi == kEpiDense ? launch_gemm_t<2, 2, kEpiDense>(a, stream) : launch_gemm_t<2, 2, kEpiFilter>(a, stream);
+    switch (gemm_tile_choice(a)) {
+        case kTileBig:
+            return epi == kEpiDense ? launch_gemm_t<2, 4, 4, 2, kEpiDense>(a, stream)
+                                    : launch_gemm_t<2, 4, 4, 2, kEpiFilter>(a, stream);
+        case kTileWide:
+            return epi == kEpiDense ? launch_gemm_t<2, 4, 2, 2, kEpiDense>(a, stream)
+                                    : launch_gemm_t<2, 4, 2, 2, kEpiFilter>(a, stream);
+        default:
+            return epi == kEpiDense ? launch_gemm_t<2, 2, 2, 2, kEpiDense>(a, stream)
+                                    : launch_gemm_t<2, 2, 2, 2, kEpiFilter>(a, stream);
+    }
 }
 
 hipError_t launch_sqnorm(const float *X, int64_t n, int d, float *out, hipStream_t stream) {

@@ -7,6 +7,7 @@ namespace knn {
 
 enum : int { kEpiDense = 0, kEpiFilter = 1 };
 enum : int { kPrecF32 = 0, kPrecBF16 = 1, kPrecFP8 = 2 };
+enum : int { kTileSmall = 0, kTileWide = 1, kTileBig = 2 };
 
 // Quantised operands (BF16 / FP8): rows padded with zeros to a multiple of
 // kQuantPad elements, so every 128-byte k-chunk load is in bounds.
@@ -60,6 +61,8 @@ struct RerankArgs {
 };
 
 hipError_t launch_dist_gemm(const DistArgs &a, int epi, hipStream_t stream);
+// Tile shape launch_dist_gemm uses for `a` (kTile*).
+int gemm_tile_choice(const DistArgs &a);
 hipError_t launch_sqnorm(const float *X, int64_t n, int d, float *out, hipStream_t stream);
 hipError_t launch_gather_rows(const float *src, int64_t n, int d, const int32_t *idx, int64_t rows, float *dst,
                               const float *norms, float *dst_norms, hipStream_t stream);

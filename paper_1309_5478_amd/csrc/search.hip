@@ -55,6 +55,7 @@ struct Carve {
 };
 
 constexpr int kSampleCols = 2048;
+constexpr int kSampleColsMax = 16384;
 constexpr int64_t kRowBlock = 32768;
 constexpr size_t kDenseBytes = size_t(1) << 30;  // materialised distance block budget
 
@@ -240,7 +241,11 @@ knn_status_t run_search(knn_handle_t h, const float *Q, int64_t m, const float *
         int64_t mu = (int64_t)(kDenseBytes / sizeof(float) / (size_t)n);
         p.Mu = mu < 1 ? 1 : (mu > m ? m : mu);
     } else {
-        p.S = n < kSampleCols ? (int)n : kSampleCols;
+        // sample columns: about 2 n / kk (at least 2048, at most 16384), so that the
+        // expected survivors of the threshold stay a few kk and within the list capacity
+        int64_t S = kSampleCols;
+        while (S < kSampleColsMax && S * p.kk < 2 * n) S *= 2;
+        p.S = n < S ? (int)n : (int)S;
         p.gathered = n > p.S;
         if (!p.gathered) {
             p.r = p.kk - 1;  // the sample is the whole corpus (own index excluded)
