@@ -192,19 +192,16 @@ __device__ __forceinline__ void mma_chunk(GemmSmem<BM, BN> &sm, int cur, uint32_
     }
 }
 
+// One output tile (tm, tn) of one product: staged K loop on the matrix cores,
+// then the dense or filter epilogue.  Called by every thread of the workgroup.
 template <int WM, int WN, int BI, int BJ, int EPI, int PREC, bool VEC>
-__global__ __launch_bounds__(64 * WM * WN) void dist_gemm_kernel(DistArgs a) {
+__device__ __forceinline__ void gemm_tile(const DistArgs &a, uint32_t tm, uint32_t tn,
+                                          GemmSmem<Tile<WM, WN, BI, BJ>::BM, Tile<WM, WN, BI, BJ>::BN> &sm) {
     using T = Tile<WM, WN, BI, BJ>;
     constexpr int NT = T::NT, BM = T::BM, BN = T::BN;
     constexpr int A4 = BM * 8 / NT;
     constexpr int B4 = BN * 8 / NT;
     static_assert(A4 >= 1 && B4 >= 1 && A4 * NT == BM * 8 && B4 * NT == BN * 8, "tile / thread mismatch");
-    __shared__ GemmSmem<BM, BN> sm;
-
-    uint32_t tm, tn;
-    bool valid;
-    tile_of_block(blockIdx.x, a.tiles_m, a.tiles_n, tm, tn, valid);
-    if (!valid) return;  // whole workgroup leaves together
     const uint32_t row0 = tm * BM, col0 = tn * BN;
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
     const uint32_t wm = wave % WM, wn = wave / WM;
@@ -295,6 +292,46 @@ __global__ __launch_bounds__(64 * WM * WN) void dist_gemm_kernel(DistArgs a) {
                     }
                 }
             }
+        }
+    }
+}
+
+template <int WM, int WN, int BI, int BJ, int EPI, int PREC, bool VEC>
+__global__ __launch_bounds__(64 * WM * WN) void dist_gemm_kernel(DistArgs a) {
+    using T = Tile<WM, WN, BI, BJ>;
+    __shared__ GemmSmem<T::BM, T::BN> sm;
+    uint32_t tm, tn;
+    bool valid;
+    tile_of_block(blockIdx.x, a.tiles_m, a.tiles_n, tm, tn, valid);
+    if (!valid) return;  // whole workgroup leaves together
+    gemm_tile<WM, WN, BI, BJ, EPI, PREC, VEC>(a, tm, tn, sm);
+}
+
+// Persistent grouped product: every workgroup pulls (job, tile) items from one
+// of eight queues -- the queue of its XCD first (block b runs on XCD b % 8),
+// then the others -- until all are empty.  Items within a queue are ordered
+// longest job first.  Counters must be zero at launch.
+template <int WM, int WN, int BI, int BJ, int EPI, int PREC, bool VEC>
+__global__ __launch_bounds__(64 * WM * WN) void dist_gemm_grouped_kernel(const DistArgs *__restrict__ jobs,
+                                                                         const GemmItem *__restrict__ items,
+                                                                         const uint32_t *__restrict__ qbegin,
+                                                                         uint32_t *__restrict__ qcount) {
+    using T = Tile<WM, WN, BI, BJ>;
+    __shared__ GemmSmem<T::BM, T::BN> sm;
+    __shared__ uint32_t next;
+    const uint32_t home = blockIdx.x % kGemmQueues;
+    for (uint32_t qi = 0; qi < kGemmQueues; ++qi) {
+        const uint32_t q = (home + qi) % kGemmQueues;
+        const uint32_t begin = qbegin[q], size = qbegin[q + 1] - begin;
+        for (;;) {
+            if (threadIdx.x == 0) next = atomicAdd(&qcount[q], 1u);
+            __syncthreads();
+            const uint32_t it = next;
+            __syncthreads();
+            if (it >= size) break;  // uniform: every thread read the same value
+            const GemmItem w = items[begin + it];
+            gemm_tile<WM, WN, BI, BJ, EPI, PREC, VEC>(jobs[w.job], w.tm, w.tn, sm);
+            __syncthreads();
         }
     }
 }
@@ -556,6 +593,27 @@ hipError_t launch_dist_gemm(const DistArgs &a, int epi, hipStream_t stream) {
             return epi == kEpiDense ? launch_gemm_t<2, 2, 2, 2, kEpiDense>(a, stream)
                                     : launch_gemm_t<2, 2, 2, 2, kEpiFilter>(a, stream);
     }
+}
+
+int gemm_grouped_grid(int num_cu) {
+    return num_cu;  // one 8-wave workgroup per CU (the tile's LDS fills it)
+}
+
+hipError_t launch_dist_gemm_grouped(const DistArgs *jobs, const GemmItem *items, const uint32_t *qbegin,
+                                    uint32_t *qcount, int prec, int epi, int num_cu, hipStream_t stream) {
+    const dim3 g(gemm_grouped_grid(num_cu)), b(Tile<2, 4, 2, 2>::NT);
+    // 128 x 256 tiles, 8 waves: one shape for every job of a batch
+    if (epi != kEpiFilter) return hipErrorInvalidValue;
+    if (prec == kPrecBF16)
+        hipLaunchKernelGGL((dist_gemm_grouped_kernel<2, 4, 2, 2, kEpiFilter, kPrecBF16, true>), g, b, 0, stream, jobs,
+                           items, qbegin, qcount);
+    else if (prec == kPrecFP8)
+        hipLaunchKernelGGL((dist_gemm_grouped_kernel<2, 4, 2, 2, kEpiFilter, kPrecFP8, true>), g, b, 0, stream, jobs,
+                           items, qbegin, qcount);
+    else
+        hipLaunchKernelGGL((dist_gemm_grouped_kernel<2, 4, 2, 2, kEpiFilter, kPrecF32, true>), g, b, 0, stream, jobs,
+                           items, qbegin, qcount);
+    return hipGetLastError();
 }
 
 hipError_t launch_sqnorm(const float *X, int64_t n, int d, float *out, hipStream_t stream) {
