@@ -90,6 +90,14 @@ typedef struct {
 /* Time every launch of the distance product with HIP events on the call's
  * stream and report it in knn_stats_t (product_ms, product_launches). */
 #define KNN_FLAG_TIMING 0x4
+/* knn_batch_search: run every step eagerly instead of capturing and replaying
+ * HIP graphs. */
+#define KNN_FLAG_NO_GRAPH 0x8
+/* Choose the tile shape of the distance product by timing the candidate shapes
+ * on the call's own operands the first time a shape class is seen (cached per
+ * handle, and in the JSON file named by KNN_AUTOTUNE_CACHE when that is set).
+ * Also enabled by the environment variable KNN_AUTOTUNE=1. */
+#define KNN_FLAG_AUTOTUNE 0x10
 
 typedef struct {
     int64_t rows;                 /* rows processed by the last call              */
@@ -192,6 +200,56 @@ knn_status_t knn_search(knn_handle_t h, const float *queries, int64_t m, const f
 knn_status_t knn_graph(knn_handle_t h, const float *points, int64_t n, int32_t d, int32_t k,
                        float *out_dist, int32_t *out_idx, void *stream,
                        const knn_options_t *opt);
+
+/*
+ * One job of knn_batch_search: the k nearest corpus points of each query, or,
+ * with queries == NULL, the k-NN graph of the corpus (m must equal n; each
+ * point's own index excluded).  All pointers are device pointers owned by the
+ * caller; rows are dense (stride d).
+ */
+typedef struct {
+    const float *queries;   /* m x d FP32, or NULL for the k-NN graph of corpus;     */
+                            /* unused when m == 0                                    */
+    int64_t m;              /* query count (>= 0)                                    */
+    const float *corpus;    /* n x d FP32                                            */
+    int64_t n;              /* corpus size (>= 1; >= 2 for a graph job)              */
+    int32_t d;              /* dimension (>= 1)                                      */
+    int32_t k;              /* 1 <= k <= 1024; k may exceed the corpus (less the own */
+                            /* point for a graph job): the missing entries of a row  */
+                            /* are +inf with index -1                                */
+    float *out_dist;        /* m x k FP32 exact squared distances           [out]    */
+    int32_t *out_idx;       /* m x k int32 corpus indices                   [out]    */
+} knn_job_t;
+
+/*
+ * knn_batch_search -- many independent k-NN problems of uneven sizes in one
+ * call (Introduction and Discussion: many simultaneous queries, each a row
+ * selection, are the coarse level of parallelism; here whole problems of
+ * different corpus sizes, dimensions and k are pooled the same way).  Each job
+ * computes exactly what knn_search (or knn_graph) computes for it, with the same
+ * output bits.  The distance products of all jobs run in one launch of
+ * (job, tile) items, one per workgroup, ordered longest job first for the
+ * round-robin dispatch of workgroups over the XCDs; the per-job threshold,
+ * flagging, selection and re-rank steps are captured into
+ * HIP graphs on the first call and replayed by later calls with the same job
+ * table, options and handle state (KNN_FLAG_NO_GRAPH runs them eagerly).
+ *
+ *   jobs     njobs job descriptions (host array, read during the call)     [in]
+ *   njobs    >= 0
+ *   stream   HIP stream of the call; the call returns after the last step is
+ *            enqueued, once the rows needing the exact fallback are known
+ *            (one host synchronisation, as knn_search)
+ *   opt      NULL for defaults; pivot, precision, oversample and the flags
+ *            FORCE_FALLBACK, UNFUSED (jobs run one by one as knn_search),
+ *            TIMING, NO_GRAPH and AUTOTUNE are honoured
+ * Errors: INVALID_VALUE for a null jobs array with njobs > 0, njobs < 0, a job
+ * with a null pointer, m < 0, n < 1, d < 1, k < 1, a graph job (null queries,
+ * m > 0) with m != n or n < 2, or a bad option; UNSUPPORTED for k > 1024 or n > INT32_MAX; the
+ * message names the first offending job.  OUT_OF_MEMORY when the batch's
+ * workspace (kept by the handle for replays) cannot be allocated.
+ */
+knn_status_t knn_batch_search(knn_handle_t h, const knn_job_t *jobs, int32_t njobs, void *stream,
+                              const knn_options_t *opt);
 
 /*
  * knn_distances -- the m x n matrix of squared Euclidean distances between the

@@ -11,7 +11,8 @@ import ctypes
 
 from . import _abi
 from ._abi import (PIVOT_LEARNED, PIVOT_PLAIN, PIVOT_SAMPLE, PREC_BF16, PREC_FP32,  # noqa: F401
-                   PREC_FP8_E4M3, FLAG_FORCE_FALLBACK, FLAG_UNFUSED, FLAG_TIMING, Options, Stats)
+                   PREC_FP8_E4M3, FLAG_FORCE_FALLBACK, FLAG_UNFUSED, FLAG_TIMING, FLAG_NO_GRAPH, FLAG_AUTOTUNE, Job, Options,
+                   Stats)
 
 _PIVOTS = {"plain": PIVOT_PLAIN, "sample": PIVOT_SAMPLE, "learned": PIVOT_LEARNED}
 _PRECS = {"fp32": PREC_FP32, "bf16": PREC_BF16, "fp8": PREC_FP8_E4M3}
@@ -134,6 +135,35 @@ class Handle:
                                         ctypes.c_void_p(dist.data_ptr()), ctypes.c_void_p(idx.data_ptr()),
                                         self._stream(), ctypes.byref(o)))
         return dist, idx
+
+    def batch_search(self, jobs, pivot="sample", precision="fp32", oversample=4, flags=0, out=None):
+        """Many independent k-NN problems in one call.  `jobs` is a list of
+        (queries, corpus, k) tuples of contiguous float32 device tensors, with
+        queries None for the k-NN graph of the corpus.  Returns a list of
+        (dist [m, k], idx [m, k]); `out` may pass that list preallocated (same
+        tensors on every call let the library replay its captured graphs)."""
+        torch = _torch()
+        arr = (Job * max(len(jobs), 1))()
+        res = []
+        for j, (q, c, kj) in enumerate(jobs):
+            for t in (c,) if q is None else (q, c):
+                if t.dim() != 2 or t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+                    raise ValueError("job tensors must be contiguous 2-D float32 device tensors")
+            n, d = c.shape
+            m = n if q is None else q.shape[0]
+            if q is not None and q.shape[1] != d:
+                raise ValueError(f"job {j}: queries and corpus differ in dimension")
+            if out is not None:
+                dist, idx = out[j]
+            else:
+                dist = torch.empty((m, kj), dtype=torch.float32, device=c.device)
+                idx = torch.empty((m, kj), dtype=torch.int32, device=c.device)
+            arr[j] = Job(0 if q is None else q.data_ptr(), m, c.data_ptr(), n, d, kj, dist.data_ptr(),
+                         idx.data_ptr())
+            res.append((dist, idx))
+        o = self._opts(pivot, precision, oversample, flags)
+        self._check(self.lib.knn_batch_search(self.h, arr, len(jobs), self._stream(), ctypes.byref(o)))
+        return res
 
     def distances(self, queries, corpus):
         """Squared Euclidean distance matrix [m, n] f32 by the norm expansion."""

@@ -18,12 +18,20 @@ PREC_FP32, PREC_BF16, PREC_FP8_E4M3 = 0, 1, 2
 FLAG_FORCE_FALLBACK = 0x1
 FLAG_UNFUSED = 0x2
 FLAG_TIMING = 0x4
+FLAG_NO_GRAPH = 0x8
+FLAG_AUTOTUNE = 0x10
 PIVOT_NPARAM = 4801
 
 
 class Options(ctypes.Structure):
     _fields_ = [("pivot", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("oversample", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+class Job(ctypes.Structure):
+    _fields_ = [("queries", ctypes.c_void_p), ("m", ctypes.c_int64), ("corpus", ctypes.c_void_p),
+                ("n", ctypes.c_int64), ("d", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("out_dist", ctypes.c_void_p), ("out_idx", ctypes.c_void_p)]
 
 
 class Stats(ctypes.Structure):
@@ -58,6 +66,7 @@ PROTOTYPES = {
     "knn_partition": (_ST, [_P, _P, _I64, _I64, _I64, _P, _P, _P, _P, _P, _P]),
     "knn_search": (_ST, [_P, _P, _I64, _P, _I64, _I32, _I32, _P, _P, _P, ctypes.POINTER(Options)]),
     "knn_graph": (_ST, [_P, _P, _I64, _I32, _I32, _P, _P, _P, ctypes.POINTER(Options)]),
+    "knn_batch_search": (_ST, [_P, ctypes.POINTER(Job), _I32, _P, ctypes.POINTER(Options)]),
     "knn_distances": (_ST, [_P, _P, _I64, _P, _I64, _I32, _P, _I64, _P]),
     "knn_get_stats": (_ST, [_P, ctypes.POINTER(Stats)]),
     "knn_pivot_set_weights": (_ST, [_P, _P, _I32]),

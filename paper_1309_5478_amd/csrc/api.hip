@@ -30,6 +30,9 @@ namespace knn {
 knn_status_t run_search(knn_handle_t h, const float *Q, int64_t m, const float *C, int64_t n, int d, int k, bool graph,
                         float *out_dist, int32_t *out_idx, hipStream_t stream, const knn_options_t *opt);
 
+knn_status_t run_batch(knn_handle_t h, const knn_job_t *jobs, int32_t njobs, hipStream_t stream,
+                       const knn_options_t *opt);
+void batch_release(knn_handle_t h);
 knn_status_t fail_msg(knn_handle_t h, knn_status_t s, const std::string &msg) { return fail(h, s, msg); }
 uint32_t *host_counter(knn_handle_t h) { return h->pinned; }
 unsigned long long *stats_ptr(knn_handle_t h) { return h->stats_dev; }
@@ -126,6 +129,7 @@ knn_status_t knn_destroy(knn_handle_t h) {
     if (!h) return KNN_SUCCESS;
     hipSetDevice(h->device);
     hipDeviceSynchronize();
+    batch_release(h);
     if (h->ws) hipFree(h->ws);
     if (h->stats_dev) hipFree(h->stats_dev);
     if (h->pinned) hipHostFree(h->pinned);
@@ -257,6 +261,30 @@ knn_status_t knn_graph(knn_handle_t h, const float *points, int64_t n, int32_t d
     hipSetDevice(h->device);
     if ((st = begin_stats(h, stream)) != KNN_SUCCESS) return st;
     return run_search(h, points, n, points, n, d, k, true, out_dist, out_idx, stream, opt);
+}
+
+knn_status_t knn_batch_search(knn_handle_t h, const knn_job_t *jobs, int32_t njobs, void *stream_,
+                              const knn_options_t *opt) {
+    if (!h) return fail(nullptr, KNN_ERROR_INVALID_VALUE, "knn_batch_search: handle is null");
+    if (njobs < 0) return fail(h, KNN_ERROR_INVALID_VALUE, "knn_batch_search: njobs < 0");
+    if (njobs > 0 && !jobs) return fail(h, KNN_ERROR_INVALID_VALUE, "knn_batch_search: jobs is null");
+    knn_status_t st = check_options(h, "knn_batch_search", opt);
+    if (st != KNN_SUCCESS) return st;
+    for (int32_t j = 0; j < njobs; ++j) {
+        const knn_job_t &b = jobs[j];
+        const std::string fn = "knn_batch_search: job " + std::to_string(j);
+        if ((st = check_points(h, fn.c_str(), b.corpus, b.n, b.d)) != KNN_SUCCESS) return st;
+        if (b.m < 0) return fail(h, KNN_ERROR_INVALID_VALUE, fn + ": m < 0");
+        if (b.k < 1) return fail(h, KNN_ERROR_INVALID_VALUE, fn + ": k < 1");
+        if (b.k > kSelectMaxK) return fail(h, KNN_ERROR_UNSUPPORTED, fn + ": k > 1024");
+        if (b.m > 0 && !b.queries && (b.m != b.n || b.n < 2))
+            return fail(h, KNN_ERROR_INVALID_VALUE, fn + ": a graph job (null queries) needs m == n >= 2");
+        if (b.m > 0 && (!b.out_dist || !b.out_idx)) return fail(h, KNN_ERROR_INVALID_VALUE, fn + ": null pointer");
+    }
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    hipSetDevice(h->device);
+    if ((st = begin_stats(h, stream)) != KNN_SUCCESS) return st;
+    return run_batch(h, jobs, njobs, stream, opt);
 }
 
 knn_status_t knn_distances(knn_handle_t h, const float *queries, int64_t m, const float *corpus, int64_t n, int32_t d,

@@ -1,0 +1,721 @@
+// knn_batch_search: many independent k-NN jobs of uneven sizes in one call.
+//
+// Every job follows the steps of knn_search (threshold from a corpus sample,
+// fused product with candidate filtering, exact fallback of unusable rows,
+// candidate selection, exact re-rank), so its output is the same.  What changes
+// is how the work reaches the device:
+//  * the fused products of all jobs run as ONE launch of (job part, row tile,
+//    column tile) items, one per workgroup, that the host orders for the
+//    hardware's round-robin dispatch over the eight XCDs: per XCD a queue of
+//    parts, longest first, a part's column range split into eight contiguous
+//    chunks, one per XCD, so each corpus tile is read by one XCD, where the
+//    part's row tiles reuse it from L2;
+//  * the per-job steps before and after it (norms, sample product, threshold
+//    selection, list flagging; candidate selection, certificate, re-rank) are
+//    captured into HIP graphs on the first call and replayed by later calls
+//    with the same job table (one graph launch per phase instead of thousands
+//    of kernel launches);
+//  * with autotuning on, the tile shape of the grouped launch is the fastest
+//    of the candidate shapes, timed on the batch itself with a threshold of
+//    -inf (nothing is kept, so the timing run has no effect on the results).
+// Jobs with more than kRowBlock queries are split into parts of at most that
+// many rows; each part has its own candidate lists.
+#include <algorithm>
+#include <cstring>
+#include <functional>
+#include <string>
+#include <vector>
+
+#include "autotune.hpp"
+#include "dist.hpp"
+#include "handle.hpp"
+#include "internal.hpp"
+#include "knn.h"
+#include "plan.hpp"
+
+namespace knn {
+
+knn_status_t fail_msg(knn_handle_t h, knn_status_t s, const std::string &msg);
+unsigned long long *stats_ptr(knn_handle_t h);
+void add_host_stats(knn_handle_t h, int64_t rows, int64_t fallback_rows);
+int handle_num_cu(knn_handle_t h);
+const uint16_t *handle_net(knn_handle_t h);
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t stream);
+hipError_t launch_sum_u32(const uint32_t *p, int64_t n, unsigned long long *out, hipStream_t stream);
+knn_status_t run_search(knn_handle_t h, const float *Q, int64_t m, const float *C, int64_t n, int d, int k, bool graph,
+                        float *out_dist, int32_t *out_idx, hipStream_t stream, const knn_options_t *opt);
+
+namespace {
+
+// dst[i] = src[i * stride], i < rows: the threshold column of a sample selection.
+__global__ __launch_bounds__(256) void column_copy_kernel(const float *__restrict__ src, int64_t stride, int64_t rows,
+                                                          float *__restrict__ dst) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < rows) dst[i] = src[i * stride];
+}
+
+hipError_t launch_column_copy(const float *src, int64_t stride, int64_t rows, float *dst, hipStream_t s) {
+    if (rows == 0) return hipSuccess;
+    hipLaunchKernelGGL(column_copy_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, src, stride, rows,
+                       dst);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+struct BatchJob {
+    const float *Q, *C;
+    int64_t m, n;
+    int d, k;
+    bool graph;
+    float *out_dist;
+    int32_t *out_idx;
+    Plan p;
+    double cost;  // 2 m n d
+    // per-job buffers
+    float *cnorm = nullptr, *qn2 = nullptr;
+    unsigned int *cmax2 = nullptr;
+    void *Cq = nullptr, *Qq = nullptr;
+    float *cs = nullptr, *qs = nullptr;
+    int first_part = 0, nparts = 0;
+};
+
+struct BatchPart {
+    int job;
+    int64_t i0, mb;
+    bool grouped;  // in the grouped launch (else its own launch: FP32 with d % 4 != 0)
+    float *tau = nullptr;
+    uint32_t *cnt = nullptr;
+    uint64_t *cand = nullptr;
+    int32_t *flags = nullptr;
+};
+
+// Buffers shared by all jobs; every use of one is ordered on the stream.
+struct BatchShared {
+    float *Cs = nullptr, *csn = nullptr, *css = nullptr, *Ds = nullptr, *tv = nullptr;
+    void *Csq = nullptr, *Qfq = nullptr;
+    int32_t *ti = nullptr;
+    float *sv = nullptr, *Qf = nullptr, *Df = nullptr, *fv = nullptr, *qfs = nullptr;
+    int32_t *si = nullptr, *fi = nullptr;
+    void *selws = nullptr;
+    float *ninf = nullptr;
+    DistArgs *table = nullptr, *probe = nullptr;
+    GemmItem *items = nullptr;
+    uint32_t *nflag = nullptr;
+};
+
+// State of the last batch of a handle: its workspace, plan and graphs.
+struct BatchState {
+    std::vector<uint8_t> key;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    uint32_t *nflag_host = nullptr;  // pinned, one count per part
+    size_t nflag_host_cap = 0;
+    hipStream_t cap_stream = nullptr;
+    std::vector<hipGraphExec_t> graphs;  // in launch order, see the segments
+    bool eager = true;                   // replay eagerly (no graphs)
+    bool timed = false;
+    std::vector<BatchJob> jobs;
+    std::vector<BatchPart> parts;
+    std::vector<int> order;  // jobs, longest first
+    BatchShared sh;
+    int tile = kTileWide;
+    size_t nitems = 0;
+    int smode = kPivotSample;
+    const uint16_t *net = nullptr;
+    int force = 0;
+
+    void drop_graphs() {
+        for (hipGraphExec_t g : graphs) hipGraphExecDestroy(g);
+        graphs.clear();
+    }
+    ~BatchState() {
+        drop_graphs();
+        if (cap_stream) hipStreamDestroy(cap_stream);
+        if (ws) hipFree(ws);
+        if (nflag_host) hipHostFree(nflag_host);
+    }
+};
+
+void batch_release(knn_handle_t h) {
+    delete h->batch;
+    h->batch = nullptr;
+}
+
+namespace {
+
+// Items of the grouped launch for a tile shape, in dispatch order.  Eight
+// queues, one per XCD, each holding the parts longest first; a part's column
+// tiles are split into eight contiguous chunks (chunk q to queue q), each
+// column tile followed by all of the part's row tiles (which then find it in
+// their XCD's L2).  Workgroup b runs on XCD b % 8 and takes the next item of
+// that queue; once a queue is empty its XCD takes items from the back of the
+// fullest remaining queue (the shortest work there).
+void build_items(const BatchState &b, int tile, std::vector<GemmItem> &items) {
+    constexpr int kQueues = 8;
+    int bm, bn;
+    gemm_tile_dims(tile, &bm, &bn);
+    std::vector<std::vector<GemmItem>> q(kQueues);
+    for (int j : b.order) {
+        const BatchJob &js = b.jobs[j];
+        for (int pi = js.first_part; pi < js.first_part + js.nparts; ++pi) {
+            const BatchPart &pt = b.parts[pi];
+            if (!pt.grouped) continue;
+            const uint32_t tm_n = (uint32_t)((pt.mb + bm - 1) / bm);
+            const uint32_t tn_n = (uint32_t)((js.n + bn - 1) / bn);
+            for (int qi = 0; qi < kQueues; ++qi) {
+                const uint32_t c0 = (uint32_t)((uint64_t)tn_n * qi / kQueues);
+                const uint32_t c1 = (uint32_t)((uint64_t)tn_n * (qi + 1) / kQueues);
+                for (uint32_t tn = c0; tn < c1; ++tn)
+                    for (uint32_t tm = 0; tm < tm_n; ++tm) q[qi].push_back(GemmItem{(uint32_t)pi, tm, tn});
+            }
+        }
+    }
+    size_t total = 0;
+    for (const auto &x : q) total += x.size();
+    items.clear();
+    items.reserve(total);
+    std::vector<size_t> head(kQueues, 0), tail(kQueues);
+    for (int qi = 0; qi < kQueues; ++qi) tail[qi] = q[qi].size();
+    for (size_t t = 0; t < total; ++t) {
+        const int qi = (int)(t % kQueues);
+        if (head[qi] < tail[qi]) {
+            items.push_back(q[qi][head[qi]++]);
+            continue;
+        }
+        int best = -1;
+        for (int o = 0; o < kQueues; ++o)
+            if (head[o] < tail[o] && (best < 0 || tail[o] - head[o] > tail[best] - head[best])) best = o;
+        items.push_back(q[best][--tail[best]]);
+    }
+}
+
+size_t max_items(const BatchState &b) {
+    // the 128 x 128 tile gives the most items
+    size_t n = 0;
+    for (const BatchPart &pt : b.parts)
+        if (pt.grouped) n += (size_t)((pt.mb + 127) / 128) * (size_t)((b.jobs[pt.job].n + 127) / 128);
+    return n;
+}
+
+// Lays out the batch workspace (sizing pass with base == nullptr).
+size_t carve_batch(Carve &c, BatchState &b, int num_cu, bool probe) {
+    BatchShared &s = b.sh;
+    size_t cs = 0, csq = 0, ds = 0, tv = 0, sv = 0, qf = 0, df = 0, fv = 0, qfq = 0, fb = 0, selws = 0, S = 0;
+    for (BatchJob &js : b.jobs) {
+        const Plan &p = js.p;
+        js.cnorm = c.take<float>(js.n);
+        js.qn2 = c.take<float>(js.m);
+        js.cmax2 = c.take<unsigned int>(1);
+        if (p.prec != kPrecF32) {
+            js.Cq = c.take<char>((size_t)js.n * p.ldq);
+            js.cs = c.take<float>(js.n);
+            if (!js.graph) {
+                js.Qq = c.take<char>((size_t)js.m * p.ldq);
+                js.qs = c.take<float>(js.m);
+            } else {
+                js.Qq = js.Cq;
+                js.qs = js.cs;
+            }
+        }
+        if (p.gathered) {
+            cs = std::max(cs, (size_t)p.S * p.d);
+            csq = std::max(csq, (size_t)p.S * p.ldq);
+        }
+        S = std::max(S, (size_t)p.S);
+        ds = std::max(ds, (size_t)p.Mb * p.S);
+        tv = std::max(tv, (size_t)p.Mb * (p.r + 1));
+        sv = std::max(sv, (size_t)p.Mb * p.kk);
+        qf = std::max(qf, (size_t)p.Fb * p.d);
+        df = std::max(df, (size_t)p.Fb * js.n);
+        fv = std::max(fv, (size_t)p.Fb * p.kk);
+        qfq = std::max(qfq, (size_t)p.Fb * p.ldq);
+        fb = std::max(fb, (size_t)p.Fb);
+        const int cap1 = select_cap_for_k(p.r + 1);
+        const int cap2 = select_cap_for_k(p.kk);
+        selws = std::max(selws, select_ws_bytes(cap1, (uint32_t)p.S, select_grid(cap1, p.Mb, num_cu)));
+        selws = std::max(selws, select_ws_bytes(cap2, (uint32_t)js.n, select_grid(cap2, p.Fb, num_cu)));
+    }
+    for (BatchPart &pt : b.parts) {
+        const Plan &p = b.jobs[pt.job].p;
+        pt.tau = c.take<float>(pt.mb);
+        pt.cnt = c.take<uint32_t>(pt.mb);
+        pt.cand = c.take<uint64_t>((size_t)pt.mb * p.cap);
+        pt.flags = c.take<int32_t>(pt.mb);
+    }
+    s.Cs = c.take<float>(cs);
+    s.csn = c.take<float>(S);
+    s.Csq = c.take<char>(csq);
+    s.css = c.take<float>(S);
+    s.Ds = c.take<float>(ds);
+    s.tv = c.take<float>(tv);
+    s.ti = c.take<int32_t>(tv);
+    s.sv = c.take<float>(sv);
+    s.si = c.take<int32_t>(sv);
+    s.Qf = c.take<float>(qf);
+    s.Df = c.take<float>(df);
+    s.fv = c.take<float>(fv);
+    s.fi = c.take<int32_t>(fv);
+    s.Qfq = c.take<char>(qfq);
+    s.qfs = c.take<float>(fb);
+    s.selws = c.take<char>(selws < 256 ? 256 : selws);
+    s.ninf = c.take<float>(1);
+    s.table = c.take<DistArgs>(b.parts.size());
+    s.probe = probe ? c.take<DistArgs>(b.parts.size()) : nullptr;
+    s.items = c.take<GemmItem>(std::max<size_t>(max_items(b), 1));
+    s.nflag = c.take<uint32_t>(b.parts.size());
+    return c.off;
+}
+
+DistArgs part_args(const BatchState &b, const BatchPart &pt) {
+    const BatchJob &js = b.jobs[pt.job];
+    const Plan &p = js.p;
+    DistArgs a{};
+    a.Q = js.Q + pt.i0 * js.d;
+    a.m = pt.mb;
+    a.C = js.C;
+    a.n = js.n;
+    a.d = js.d;
+    a.cnorm = js.cnorm;
+    a.self_offset = js.graph ? pt.i0 : -1;
+    a.tau = pt.tau;
+    a.tau_stride = 1;
+    a.cnt = pt.cnt;
+    a.cand = pt.cand;
+    a.cap = p.cap;
+    a.prec = p.prec;
+    a.Qq = js.Qq ? static_cast<const char *>(js.Qq) + pt.i0 * p.ldq : nullptr;
+    a.Cq = js.Cq;
+    a.ldq = p.ldq;
+    a.qscale = js.qs ? js.qs + pt.i0 : nullptr;
+    a.cscale = js.cs;
+    return a;
+}
+
+// ---- the phases, enqueued on a stream (captured or eager) ------------------
+hipError_t enqueue_prep(const BatchState &b, int num_cu, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    const BatchShared &sh = b.sh;
+#define BTRY(call)                                 \
+    do {                                           \
+        if ((e = (call)) != hipSuccess) return e;  \
+    } while (0)
+    for (int j : b.order) {
+        const BatchJob &js = b.jobs[j];
+        const Plan &p = js.p;
+        if (js.nparts == 0) continue;
+        BTRY(launch_sqnorm(js.C, js.n, js.d, js.cnorm, s));
+        BTRY(launch_sqnorm(js.Q, js.m, js.d, js.qn2, s));
+        BTRY(launch_fill_u32(js.cmax2, 1, 0u, s));
+        BTRY(launch_max_nonneg(js.cnorm, js.n, js.cmax2, s));
+        if (p.prec != kPrecF32) {
+            BTRY(launch_quantize(js.C, js.n, js.d, p.prec, js.Cq, js.cs, s));
+            if (!js.graph) BTRY(launch_quantize(js.Q, js.m, js.d, p.prec, js.Qq, js.qs, s));
+        }
+        const float *Cs = js.C, *csn = js.cnorm, *css = js.cs;
+        const void *Csq = js.Cq;
+        if (p.gathered) {
+            BTRY(launch_gather_rows(js.C, js.n, js.d, nullptr, p.S, sh.Cs, js.cnorm, sh.csn, s));
+            Cs = sh.Cs;
+            csn = sh.csn;
+            if (p.prec != kPrecF32) {
+                BTRY(launch_quantize(sh.Cs, p.S, js.d, p.prec, sh.Csq, sh.css, s));
+                Csq = sh.Csq;
+                css = sh.css;
+            }
+        }
+        for (int pi = js.first_part; pi < js.first_part + js.nparts; ++pi) {
+            const BatchPart &pt = b.parts[pi];
+            DistArgs sa = part_args(b, pt);
+            sa.C = Cs;
+            sa.n = p.S;
+            sa.cnorm = csn;
+            sa.self_offset = (js.graph && !p.gathered) ? pt.i0 : -1;
+            sa.out = sh.Ds;
+            sa.ldo = p.S;
+            sa.tau = nullptr;
+            sa.cnt = nullptr;
+            sa.cand = nullptr;
+            sa.Cq = Csq;
+            sa.cscale = css;
+            BTRY(launch_dist_gemm(sa, kEpiDense, s));
+            BTRY(select_dense(sh.Ds, pt.mb, p.S, p.S, p.r + 1, sh.tv, sh.ti, sh.selws, num_cu, b.smode, b.net, s));
+            BTRY(launch_column_copy(sh.tv + p.r, p.r + 1, pt.mb, pt.tau, s));
+            BTRY(launch_fill_u32(pt.cnt, pt.mb, 0u, s));
+        }
+    }
+    return e;
+}
+
+hipError_t enqueue_product(const BatchState &b, const DistArgs *table, int tile, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    BTRY(launch_dist_gemm_grouped(table, b.sh.items, (int64_t)b.nitems, b.jobs[0].p.prec, tile, s));
+    for (const BatchPart &pt : b.parts) {
+        if (pt.grouped) continue;
+        DistArgs fa = part_args(b, pt);
+        if (table == b.sh.probe) {
+            fa.tau = b.sh.ninf;
+            fa.tau_stride = 0;
+        }
+        BTRY(launch_dist_gemm(fa, kEpiFilter, s));
+    }
+    return e;
+}
+
+hipError_t enqueue_flags(const BatchState &b, knn_handle_t h, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    BTRY(launch_fill_u32(b.sh.nflag, (int64_t)b.parts.size(), 0u, s));
+    for (size_t pi = 0; pi < b.parts.size(); ++pi) {
+        const BatchPart &pt = b.parts[pi];
+        const Plan &p = b.jobs[pt.job].p;
+        BTRY(launch_sum_u32(pt.cnt, pt.mb, stats_ptr(h) + kStatCandidates, s));
+        BTRY(launch_flag_rows(pt.cnt, pt.mb, (uint32_t)p.kk, (uint32_t)p.cap, b.force, b.sh.nflag + pi, pt.flags, s));
+    }
+    return hipMemcpyAsync(b.nflag_host, b.sh.nflag, b.parts.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+}
+
+hipError_t enqueue_final(const BatchState &b, knn_handle_t h, int num_cu, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    const BatchShared &sh = b.sh;
+    for (int j : b.order) {
+        const BatchJob &js = b.jobs[j];
+        const Plan &p = js.p;
+        for (int pi = js.first_part; pi < js.first_part + js.nparts; ++pi) {
+            const BatchPart &pt = b.parts[pi];
+            SelectArgs ka{};
+            ka.keys = pt.cand;
+            ka.key_cnt = pt.cnt;
+            ka.rows = pt.mb;
+            ka.cols = (uint32_t)p.cap;
+            ka.ld = p.cap;
+            ka.k = (uint32_t)p.kk;
+            ka.out_val = sh.sv;
+            ka.out_idx = sh.si;
+            ka.mode = b.smode;
+            ka.net = b.smode == kPivotLearned ? b.net : nullptr;
+            BTRY(launch_select_keys(ka, pt.mb, num_cu, s));
+            if (p.kk < p.n_eff)
+                BTRY(launch_certify(sh.sv, pt.mb, p.kk, js.k, js.qn2 + pt.i0, js.cmax2, p.rel,
+                                    stats_ptr(h) + kStatUncertified, s));
+            RerankArgs rr{js.Q + pt.i0 * js.d, pt.mb, js.C, js.n, js.d, sh.si, (uint32_t)p.kk, js.k,
+                          js.out_dist + pt.i0 * js.k, js.out_idx + pt.i0 * js.k};
+            BTRY(launch_rerank(rr, s));
+        }
+    }
+    return e;
+}
+
+// Exact re-do of the flagged rows of every part (after the flag counts reached
+// the host), as in knn_search.
+hipError_t run_fallback(const BatchState &b, int num_cu, hipStream_t s, int64_t *total) {
+    hipError_t e = hipSuccess;
+    const BatchShared &sh = b.sh;
+    for (size_t pi = 0; pi < b.parts.size(); ++pi) {
+        const int64_t nf = b.nflag_host[pi];
+        if (nf == 0) continue;
+        *total += nf;
+        const BatchPart &pt = b.parts[pi];
+        const BatchJob &js = b.jobs[pt.job];
+        const Plan &p = js.p;
+        const float *Qb = js.Q + pt.i0 * js.d;
+        for (int64_t f0 = 0; f0 < nf; f0 += p.Fb) {
+            const int64_t fb = nf - f0 < p.Fb ? nf - f0 : p.Fb;
+            BTRY(launch_gather_rows(Qb, pt.mb, js.d, pt.flags + f0, fb, sh.Qf, nullptr, nullptr, s));
+            if (p.prec != kPrecF32) BTRY(launch_quantize(sh.Qf, fb, js.d, p.prec, sh.Qfq, sh.qfs, s));
+            DistArgs da{};
+            da.Q = sh.Qf;
+            da.m = fb;
+            da.C = js.C;
+            da.n = js.n;
+            da.d = js.d;
+            da.cnorm = js.cnorm;
+            da.self_offset = js.graph ? pt.i0 : -1;
+            da.row_ids = pt.flags + f0;
+            da.out = sh.Df;
+            da.ldo = js.n;
+            da.prec = p.prec;
+            da.Qq = sh.Qfq;
+            da.Cq = js.Cq;
+            da.ldq = p.ldq;
+            da.qscale = sh.qfs;
+            da.cscale = js.cs;
+            BTRY(launch_dist_gemm(da, kEpiDense, s));
+            BTRY(select_dense(sh.Df, fb, js.n, js.n, p.kk, sh.fv, sh.fi, sh.selws, num_cu, b.smode, b.net, s));
+            BTRY(launch_scatter_fallback(pt.flags + f0, fb, sh.fv, sh.fi, p.kk, pt.cand, pt.cnt, p.cap, s));
+        }
+    }
+    return e;
+}
+#undef BTRY
+
+// Captures `fn` enqueued on the state's capture stream into an executable graph.
+hipError_t capture(BatchState &b, const std::function<hipError_t(hipStream_t)> &fn, hipGraphExec_t *out) {
+    *out = nullptr;
+    hipError_t e = hipStreamBeginCapture(b.cap_stream, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) return e;
+    hipError_t fe = fn(b.cap_stream);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(b.cap_stream, &g);
+    if (fe != hipSuccess) e = fe;
+    if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    if (g) hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        *out = nullptr;
+        (void)hipGetLastError();
+    }
+    return e;
+}
+
+std::vector<uint8_t> make_key(const knn_job_t *jobs, int32_t njobs, const knn_options_t &o, int smode,
+                              const uint16_t *net, const void *ws) {
+    std::vector<uint8_t> k(sizeof(knn_job_t) * (size_t)njobs + sizeof(o) + sizeof(smode) + 2 * sizeof(void *));
+    uint8_t *p = k.data();
+    std::memcpy(p, jobs, sizeof(knn_job_t) * (size_t)njobs);
+    p += sizeof(knn_job_t) * (size_t)njobs;
+    std::memcpy(p, &o, sizeof(o));
+    p += sizeof(o);
+    std::memcpy(p, &smode, sizeof(smode));
+    p += sizeof(smode);
+    std::memcpy(p, &net, sizeof(void *));
+    p += sizeof(void *);
+    std::memcpy(p, &ws, sizeof(void *));
+    return k;
+}
+
+}  // namespace
+
+knn_status_t run_batch(knn_handle_t h, const knn_job_t *jobs, int32_t njobs, hipStream_t stream,
+                       const knn_options_t *opt_in) {
+    knn_options_t o{};
+    o.pivot = kPivotSample;
+    if (opt_in) o = *opt_in;
+    const int num_cu = handle_num_cu(h);
+    const uint16_t *net = handle_net(h);
+    int smode = o.pivot;
+    if (smode == kPivotLearned && !net) smode = kPivotSample;
+
+    hipError_t e;
+#define KTRY(call)                                                                                       \
+    do {                                                                                                 \
+        if ((e = (call)) != hipSuccess)                                                                  \
+            return fail_msg(h, KNN_ERROR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e));     \
+    } while (0)
+
+    if (o.flags & KNN_FLAG_UNFUSED) {  // one job after the other, as knn_search
+        for (int32_t j = 0; j < njobs; ++j) {
+            const knn_job_t &jb = jobs[j];
+            if (jb.m == 0) continue;
+            const bool graph = jb.queries == nullptr;  // m > 0 here
+            knn_status_t st = run_search(h, graph ? jb.corpus : jb.queries, jb.m, jb.corpus, jb.n, jb.d, jb.k, graph,
+                                         jb.out_dist, jb.out_idx, stream, &o);
+            if (st != KNN_SUCCESS) return st;
+        }
+        return KNN_SUCCESS;
+    }
+
+    if (!h->batch) h->batch = new BatchState();
+    BatchState &b = *h->batch;
+    std::vector<uint8_t> key = make_key(jobs, njobs, o, smode, net, b.ws);
+    const bool timed = (o.flags & KNN_FLAG_TIMING) != 0;
+    const bool want_graph = (o.flags & KNN_FLAG_NO_GRAPH) == 0;
+
+    if (key != b.key || b.ws == nullptr) {
+        // ---- plan the batch ----
+        KTRY(hipDeviceSynchronize());  // earlier batches may still use the graphs and workspace
+        b.drop_graphs();
+        b.key.clear();
+        b.jobs.clear();
+        b.parts.clear();
+        b.smode = smode;
+        b.net = net;
+        b.force = (o.flags & KNN_FLAG_FORCE_FALLBACK) ? 1 : 0;
+        b.timed = timed;
+        for (int32_t j = 0; j < njobs; ++j) {
+            const knn_job_t &jb = jobs[j];
+            BatchJob js{};
+            js.graph = jb.queries == nullptr && jb.m > 0;
+            js.Q = js.graph ? jb.corpus : jb.queries;
+            js.C = jb.corpus;
+            js.m = jb.m;
+            js.n = jb.n;
+            js.d = jb.d;
+            js.k = jb.k;
+            js.out_dist = jb.out_dist;
+            js.out_idx = jb.out_idx;
+            js.p = make_plan(jb.m > 0 ? jb.m : 1, jb.n, jb.d, jb.k, js.graph, &o, kRowBlock);
+            js.cost = 2.0 * (double)jb.m * (double)jb.n * jb.d;
+            js.first_part = (int)b.parts.size();
+            for (int64_t i0 = 0; i0 < jb.m; i0 += js.p.Mb) {
+                BatchPart pt{};
+                pt.job = j;
+                pt.i0 = i0;
+                pt.mb = jb.m - i0 < js.p.Mb ? jb.m - i0 : js.p.Mb;
+                pt.grouped = !(js.p.prec == kPrecF32 && js.d % 4 != 0);
+                b.parts.push_back(pt);
+            }
+            js.nparts = (int)b.parts.size() - js.first_part;
+            b.jobs.push_back(js);
+        }
+        b.order.resize(b.jobs.size());
+        for (size_t j = 0; j < b.jobs.size(); ++j) b.order[j] = (int)j;
+        std::stable_sort(b.order.begin(), b.order.end(),
+                         [&](int x, int y) { return b.jobs[x].cost > b.jobs[y].cost; });
+        if (b.parts.empty()) return KNN_SUCCESS;
+
+        const bool tune = autotune_enabled(&o);
+        Carve sizing{nullptr};
+        const size_t bytes = carve_batch(sizing, b, num_cu, tune);
+        if (bytes > b.ws_bytes) {
+            if (b.ws) {
+                hipFree(b.ws);
+                b.ws = nullptr;
+                b.ws_bytes = 0;
+            }
+            if (hipMalloc(&b.ws, bytes) != hipSuccess) {
+                b.ws = nullptr;
+                (void)hipGetLastError();
+                return fail_msg(h, KNN_ERROR_OUT_OF_MEMORY,
+                                "knn_batch_search: workspace of " + std::to_string(bytes) + " bytes");
+            }
+            b.ws_bytes = bytes;
+        }
+        Carve real{static_cast<char *>(b.ws)};
+        carve_batch(real, b, num_cu, tune);
+        if (b.parts.size() > b.nflag_host_cap) {
+            if (b.nflag_host) hipHostFree(b.nflag_host);
+            b.nflag_host = nullptr;
+            b.nflag_host_cap = 0;
+            if (hipHostMalloc(&b.nflag_host, b.parts.size() * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+                b.nflag_host = nullptr;
+                (void)hipGetLastError();
+                return fail_msg(h, KNN_ERROR_OUT_OF_MEMORY, "knn_batch_search: pinned host buffer");
+            }
+            b.nflag_host_cap = b.parts.size();
+        }
+        if (!b.cap_stream) KTRY(hipStreamCreateWithFlags(&b.cap_stream, hipStreamNonBlocking));
+
+        // ---- device tables ----
+        std::vector<DistArgs> table(b.parts.size());
+        for (size_t pi = 0; pi < b.parts.size(); ++pi) table[pi] = part_args(b, b.parts[pi]);
+        KTRY(hipMemcpyAsync(b.sh.table, table.data(), table.size() * sizeof(DistArgs), hipMemcpyHostToDevice, stream));
+        KTRY(launch_fill_u32(reinterpret_cast<uint32_t *>(b.sh.ninf), 1, 0xFF800000u, stream));
+        const int prec = b.jobs[0].p.prec;
+        b.tile = prec == kPrecFP8 ? kTileWide : kTileBig;
+        std::vector<GemmItem> items;
+        int uploaded = -1;
+        auto upload = [&](int tile) -> hipError_t {
+            if (tile == uploaded) return hipSuccess;
+            build_items(b, tile, items);
+            b.nitems = items.size();
+            hipError_t ue = hipSuccess;
+            if (!items.empty())
+                ue = hipMemcpyAsync(b.sh.items, items.data(), items.size() * sizeof(GemmItem), hipMemcpyHostToDevice,
+                                    stream);
+            if (ue == hipSuccess) ue = hipStreamSynchronize(stream);  // host vectors change on the next upload
+            if (ue == hipSuccess) uploaded = tile;
+            return ue;
+        };
+        if (tune) {
+            // key: device, precision, work-weighted dimension and corpus size, total work
+            double w = 0, wd = 0, wn = 0;
+            for (const BatchJob &js : b.jobs) {
+                w += js.cost;
+                wd += js.cost * js.d;
+                wn += js.cost * (double)js.n;
+            }
+            w = w > 0 ? w : 1;
+            const std::string tkey = "grouped|" + h->arch + "|cu" + std::to_string(num_cu) + "|p" +
+                                     std::to_string(prec) + "|d" + std::to_string(size_bucket((int64_t)(wd / w))) +
+                                     "|n" + std::to_string(size_bucket((int64_t)(wn / w))) + "|f" +
+                                     std::to_string(size_bucket((int64_t)(w / 1e6)));
+            int choice = autotune_lookup(tkey);
+            if (choice < 0) {
+                std::vector<DistArgs> probe = table;
+                for (DistArgs &a : probe) {
+                    a.tau = b.sh.ninf;
+                    a.tau_stride = 0;
+                }
+                KTRY(hipMemcpyAsync(b.sh.probe, probe.data(), probe.size() * sizeof(DistArgs), hipMemcpyHostToDevice,
+                                    stream));
+                KTRY(hipStreamSynchronize(stream));
+                std::vector<int> cands = {kTileSmall, kTileWide};
+                if (prec != kPrecFP8) cands.push_back(kTileBig);
+                auto run = [&](int tile) -> hipError_t {
+                    hipError_t re = upload(tile);
+                    if (re == hipSuccess) re = enqueue_product(b, b.sh.probe, tile, stream);
+                    return re;
+                };
+                KTRY(autotune_pick(tkey, cands, run, stream, 2, &choice));
+            }
+            b.tile = choice;
+        }
+        KTRY(upload(b.tile));
+
+        // ---- graphs: prep (+ product + flags), then final ----
+        b.eager = true;
+        if (want_graph) {
+            std::vector<hipGraphExec_t> gs;
+            hipGraphExec_t g = nullptr;
+            bool ok = true;
+            if (timed) {
+                ok = capture(b, [&](hipStream_t s) { return enqueue_prep(b, num_cu, s); }, &g) == hipSuccess;
+                if (ok) gs.push_back(g);
+                ok = ok && capture(b, [&](hipStream_t s) { return enqueue_flags(b, h, s); }, &g) == hipSuccess;
+                if (ok) gs.push_back(g);
+            } else {
+                ok = capture(b, [&](hipStream_t s) {
+                         hipError_t ce = enqueue_prep(b, num_cu, s);
+                         if (ce == hipSuccess) ce = enqueue_product(b, b.sh.table, b.tile, s);
+                         if (ce == hipSuccess) ce = enqueue_flags(b, h, s);
+                         return ce;
+                     }, &g) == hipSuccess;
+                if (ok) gs.push_back(g);
+            }
+            ok = ok && capture(b, [&](hipStream_t s) { return enqueue_final(b, h, num_cu, s); }, &g) == hipSuccess;
+            if (ok) gs.push_back(g);
+            if (ok) {
+                b.graphs = gs;
+                b.eager = false;
+            } else {
+                for (hipGraphExec_t x : gs) hipGraphExecDestroy(x);  // capture failed: eager steps
+            }
+        }
+        b.key = make_key(jobs, njobs, o, smode, net, b.ws);
+    }
+
+    // ---- run ----
+    int64_t rows = 0;
+    for (const BatchJob &js : b.jobs) rows += js.m;
+    ProductTimer timer;
+    KTRY(timer.init(timed));
+    double flops = 0;
+    for (const BatchJob &js : b.jobs) flops += js.cost;
+    if (b.eager) {
+        KTRY(enqueue_prep(b, num_cu, stream));
+        KTRY(timer.begin(stream, flops));
+        KTRY(enqueue_product(b, b.sh.table, b.tile, stream));
+        KTRY(timer.end(stream));
+        KTRY(enqueue_flags(b, h, stream));
+    } else if (timed) {
+        KTRY(hipGraphLaunch(b.graphs[0], stream));
+        KTRY(timer.begin(stream, flops));
+        KTRY(enqueue_product(b, b.sh.table, b.tile, stream));
+        KTRY(timer.end(stream));
+        KTRY(hipGraphLaunch(b.graphs[1], stream));
+    } else {
+        KTRY(hipGraphLaunch(b.graphs[0], stream));
+    }
+    KTRY(hipStreamSynchronize(stream));
+    KTRY(timer.collect(h));
+    int64_t fallback = 0;
+    KTRY(run_fallback(b, num_cu, stream, &fallback));
+    if (b.eager)
+        KTRY(enqueue_final(b, h, num_cu, stream));
+    else
+        KTRY(hipGraphLaunch(b.graphs.back(), stream));
+#undef KTRY
+    add_host_stats(h, rows, fallback);
+    return KNN_SUCCESS;
+}
+
+}  // namespace knn

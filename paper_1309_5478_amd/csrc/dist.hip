@@ -307,33 +307,32 @@ __global__ __launch_bounds__(64 * WM * WN) void dist_gemm_kernel(DistArgs a) {
     gemm_tile<WM, WN, BI, BJ, EPI, PREC, VEC>(a, tm, tn, sm);
 }
 
-// Persistent grouped product: every workgroup pulls (job, tile) items from one
-// of eight queues -- the queue of its XCD first (block b runs on XCD b % 8),
-// then the others -- until all are empty.  Items within a queue are ordered
-// longest job first.  Counters must be zero at launch.
+// A structure at an address that is the same in every lane, held in scalar
+// registers (vector loads of the same words, then the first lane's copy).
+template <class T>
+__device__ __forceinline__ T uniform_load(const T *p) {
+    static_assert(sizeof(T) % 4 == 0, "whole dwords");
+    T v;
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(p);
+    uint32_t *dst = reinterpret_cast<uint32_t *>(&v);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
+    return v;
+}
+
+// Grouped product: workgroup b computes item b of a list of (job, row tile,
+// column tile) items that the host has put in dispatch order (workgroup b runs
+// on XCD b % 8).  One item per workgroup, as in the single product: a
+// persistent loop over items would keep the tile set-up live across items and
+// spill.
 template <int WM, int WN, int BI, int BJ, int EPI, int PREC, bool VEC>
 __global__ __launch_bounds__(64 * WM * WN) void dist_gemm_grouped_kernel(const DistArgs *__restrict__ jobs,
-                                                                         const GemmItem *__restrict__ items,
-                                                                         const uint32_t *__restrict__ qbegin,
-                                                                         uint32_t *__restrict__ qcount) {
+                                                                         const GemmItem *__restrict__ items) {
     using T = Tile<WM, WN, BI, BJ>;
     __shared__ GemmSmem<T::BM, T::BN> sm;
-    __shared__ uint32_t next;
-    const uint32_t home = blockIdx.x % kGemmQueues;
-    for (uint32_t qi = 0; qi < kGemmQueues; ++qi) {
-        const uint32_t q = (home + qi) % kGemmQueues;
-        const uint32_t begin = qbegin[q], size = qbegin[q + 1] - begin;
-        for (;;) {
-            if (threadIdx.x == 0) next = atomicAdd(&qcount[q], 1u);
-            __syncthreads();
-            const uint32_t it = next;
-            __syncthreads();
-            if (it >= size) break;  // uniform: every thread read the same value
-            const GemmItem w = items[begin + it];
-            gemm_tile<WM, WN, BI, BJ, EPI, PREC, VEC>(jobs[w.job], w.tm, w.tn, sm);
-            __syncthreads();
-        }
-    }
+    const GemmItem w = uniform_load(items + blockIdx.x);
+    const DistArgs a = uniform_load(jobs + w.job);
+    gemm_tile<WM, WN, BI, BJ, EPI, PREC, VEC>(a, w.tm, w.tn, sm);
 }
 
 // ---- squared norms, one wave per point, fixed lane-tree order -------------
@@ -570,6 +569,7 @@ static hipError_t launch_gemm_t(const DistArgs &a0, hipStream_t stream) {
 // device with such tiles (wide for FP8), small otherwise.  KNN_GEMM_TILE
 // (small / wide / big) overrides the default where the shape is legal.
 int gemm_tile_choice(const DistArgs &a) {
+    if (a.tile >= kTileSmall && a.tile <= kTileBig) return (a.tile == kTileBig && a.prec == kPrecFP8) ? kTileWide : a.tile;
     const bool large = a.m >= 2048 && a.n >= 2048;
     int t = large ? (a.prec == kPrecFP8 ? kTileWide : kTileBig) : kTileSmall;
     if (const char *e = std::getenv("KNN_GEMM_TILE")) {
@@ -595,25 +595,47 @@ hipError_t launch_dist_gemm(const DistArgs &a, int epi, hipStream_t stream) {
     }
 }
 
-int gemm_grouped_grid(int num_cu) {
-    return num_cu;  // one 8-wave workgroup per CU (the tile's LDS fills it)
+void gemm_tile_dims(int tile, int *bm, int *bn) {
+    switch (tile) {
+        case kTileBig: *bm = Tile<2, 4, 4, 2>::BM; *bn = Tile<2, 4, 4, 2>::BN; break;
+        case kTileWide: *bm = Tile<2, 4, 2, 2>::BM; *bn = Tile<2, 4, 2, 2>::BN; break;
+        default: *bm = Tile<2, 2, 2, 2>::BM; *bn = Tile<2, 2, 2, 2>::BN; break;
+    }
 }
 
-hipError_t launch_dist_gemm_grouped(const DistArgs *jobs, const GemmItem *items, const uint32_t *qbegin,
-                                    uint32_t *qcount, int prec, int epi, int num_cu, hipStream_t stream) {
-    const dim3 g(gemm_grouped_grid(num_cu)), b(Tile<2, 4, 2, 2>::NT);
-    // 128 x 256 tiles, 8 waves: one shape for every job of a batch
-    if (epi != kEpiFilter) return hipErrorInvalidValue;
+template <int WM, int WN, int BI, int BJ>
+static hipError_t launch_grouped_t(const DistArgs *jobs, const GemmItem *items, int64_t grid, int prec,
+                                   hipStream_t stream) {
+    const dim3 g((unsigned)grid), b(Tile<WM, WN, BI, BJ>::NT);
     if (prec == kPrecBF16)
-        hipLaunchKernelGGL((dist_gemm_grouped_kernel<2, 4, 2, 2, kEpiFilter, kPrecBF16, true>), g, b, 0, stream, jobs,
-                           items, qbegin, qcount);
-    else if (prec == kPrecFP8)
-        hipLaunchKernelGGL((dist_gemm_grouped_kernel<2, 4, 2, 2, kEpiFilter, kPrecFP8, true>), g, b, 0, stream, jobs,
-                           items, qbegin, qcount);
-    else
-        hipLaunchKernelGGL((dist_gemm_grouped_kernel<2, 4, 2, 2, kEpiFilter, kPrecF32, true>), g, b, 0, stream, jobs,
-                           items, qbegin, qcount);
+        hipLaunchKernelGGL((dist_gemm_grouped_kernel<WM, WN, BI, BJ, kEpiFilter, kPrecBF16, true>), g, b, 0, stream,
+                           jobs, items);
+    else if (prec == kPrecFP8) {
+        if constexpr (BI * BJ <= 4)
+            hipLaunchKernelGGL((dist_gemm_grouped_kernel<WM, WN, BI, BJ, kEpiFilter, kPrecFP8, true>), g, b, 0, stream,
+                               jobs, items);
+        else
+            return hipErrorInvalidValue;
+    } else
+        hipLaunchKernelGGL((dist_gemm_grouped_kernel<WM, WN, BI, BJ, kEpiFilter, kPrecF32, true>), g, b, 0, stream,
+                           jobs, items);
     return hipGetLastError();
+}
+
+hipError_t launch_dist_gemm_grouped(const DistArgs *jobs, const GemmItem *items, int64_t nitems, int prec, int tile,
+                                    hipStream_t stream) {
+    if (nitems == 0) return hipSuccess;
+    if (nitems > 0x7fffffff) return hipErrorInvalidValue;
+    const int64_t grid = nitems;
+    switch (tile) {
+        case kTileBig:
+            if (prec == kPrecFP8) return hipErrorInvalidValue;  // FP8 has no 256 x 256 instance
+            if (prec == kPrecBF16)
+                return launch_grouped_t<2, 4, 4, 2>(jobs, items, grid, kPrecBF16, stream);
+            return launch_grouped_t<2, 4, 4, 2>(jobs, items, grid, kPrecF32, stream);
+        case kTileWide: return launch_grouped_t<2, 4, 2, 2>(jobs, items, grid, prec, stream);
+        default: return launch_grouped_t<2, 2, 2, 2>(jobs, items, grid, prec, stream);
+    }
 }
 
 hipError_t launch_sqnorm(const float *X, int64_t n, int d, float *out, hipStream_t stream) {

@@ -43,6 +43,8 @@ struct DistArgs {
     int64_t ldq;
     const float *qscale;
     const float *cscale;
+    // tile shape (kTile*), or -1 for the default choice of gemm_tile_choice
+    int tile = -1;
     // filled by the launcher
     uint32_t tiles_m, tiles_n;
 };
@@ -62,18 +64,18 @@ struct RerankArgs {
 
 hipError_t launch_dist_gemm(const DistArgs &a, int epi, hipStream_t stream);
 
-// ---- grouped persistent product (batches) ----------------------------------
-constexpr int kGemmQueues = 8;           // one work queue per XCD
-constexpr int kGroupedBM = 128;          // tile of the grouped product
-constexpr int kGroupedBN = 256;
+// ---- grouped product (batches) ---------------------------------------------
 struct GemmItem {
     uint32_t job, tm, tn;
 };
-// jobs: device array of DistArgs (tiles_m / tiles_n unused); items: device
-// array; qbegin: kGemmQueues + 1 offsets into items; qcount: kGemmQueues
-// counters, zero at launch.  Needs d % 4 == 0 for FP32 jobs.
-hipError_t launch_dist_gemm_grouped(const DistArgs *jobs, const GemmItem *items, const uint32_t *qbegin,
-                                    uint32_t *qcount, int prec, int epi, int num_cu, hipStream_t stream);
+// Rows x columns of a tile shape (kTile*).
+void gemm_tile_dims(int tile, int *bm, int *bn);
+// One workgroup per item: jobs is a device array of DistArgs (tiles_m /
+// tiles_n / tile unused), items a device array of nitems tiles of the shape
+// `tile`, in dispatch order (item b runs on XCD b % 8).  FP32 jobs need
+// d % 4 == 0.  FILTER epilogue only.
+hipError_t launch_dist_gemm_grouped(const DistArgs *jobs, const GemmItem *items, int64_t nitems, int prec, int tile,
+                                    hipStream_t stream);
 // Tile shape launch_dist_gemm uses for `a` (kTile*).
 int gemm_tile_choice(const DistArgs &a);
 hipError_t launch_sqnorm(const float *X, int64_t n, int d, float *out, hipStream_t stream);

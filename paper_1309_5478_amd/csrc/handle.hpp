@@ -6,6 +6,10 @@
 
 #include "knn.h"
 
+namespace knn {
+struct BatchState;  // batch.hip
+}
+
 struct knn_handle_s {
     int device = 0;
     int num_cu = 0;
@@ -28,5 +32,7 @@ struct knn_handle_s {
     int64_t net_step = 0;
     bool has_net = false;
     float net_quantile = 0.9f;
+    // plan, workspace and graphs of the last knn_batch_search
+    knn::BatchState *batch = nullptr;
 };
 

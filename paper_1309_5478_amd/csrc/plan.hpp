@@ -70,6 +70,7 @@ struct Bufs {
     int32_t *fi = nullptr;
     float *Dm = nullptr;
     void *selws = nullptr;
+    float *ninf = nullptr;  // one -inf: threshold of the tile-timing launches
 };
 
 inline size_t carve(Carve &c, const Plan &p, Bufs &b, int num_cu) {
@@ -122,6 +123,7 @@ inline size_t carve(Carve &c, const Plan &p, Bufs &b, int num_cu) {
         selws = w1 > w2 ? w1 : w2;
     }
     b.selws = c.take<char>(selws < 256 ? 256 : selws);
+    b.ninf = c.take<float>(1);
     return c.off;
 }
 
@@ -206,23 +208,32 @@ inline Plan make_plan(int64_t m, int64_t n, int d, int k, bool graph, const knn_
         int64_t mu = (int64_t)(kDenseBytes / sizeof(float) / (size_t)n);
         p.Mu = mu < 1 ? 1 : (mu > m ? m : mu);
     } else {
-        // sample columns: about 2 n / kk (at least 2048, at most 16384), so that the
-        // expected survivors of the threshold stay a few kk and within the list capacity
+        // sample columns: at least 2 n / kk (from 2048 up to 16384), and more while the
+        // expected survivors of the threshold would exceed half the largest list
+        // capacity, so that the candidate lists stay a few kk long and rarely overflow
+        auto rank_for = [&](int64_t S, double &expected) -> int {
+            if (n <= S) {
+                expected = (double)p.kk;
+                return p.kk - 1;  // the sample is the whole corpus (own index excluded)
+            }
+            const double mu = (double)S * p.kk / (double)p.n_eff;
+            int64_t ri = (int64_t)std::ceil(mu + 3.0 * std::sqrt(mu) + 4.0);
+            if (ri > S - 1) ri = S - 1;
+            if (ri > kSelectMaxK - 1) ri = kSelectMaxK - 1;
+            expected = (double)(ri + 1) * (double)p.n_eff / (double)S;
+            return (int)ri;
+        };
         int64_t S = kSampleCols;
-        while (S < kSampleColsMax && S * p.kk < 2 * n) S *= 2;
+        double expected = 0;
+        for (;;) {
+            rank_for(S, expected);
+            const bool enough = S * p.kk >= 2 * n && 2.0 * expected <= kSelectKeysCap;
+            if (enough || S >= kSampleColsMax || S >= n) break;
+            S *= 2;
+        }
         p.S = n < S ? (int)n : (int)S;
         p.gathered = n > p.S;
-        if (!p.gathered) {
-            p.r = p.kk - 1;  // the sample is the whole corpus (own index excluded)
-        } else {
-            double mu = (double)p.S * p.kk / (double)p.n_eff;
-            double r = std::ceil(mu + 3.0 * std::sqrt(mu) + 4.0);
-            int64_t ri = (int64_t)r;
-            if (ri > p.S - 1) ri = p.S - 1;
-            if (ri > kSelectMaxK - 1) ri = kSelectMaxK - 1;
-            p.r = (int)ri;
-        }
-        double expected = p.gathered ? (double)(p.r + 1) * (double)p.n_eff / p.S : (double)p.kk;
+        p.r = rank_for(p.S, expected);
         int64_t cap = (int64_t)(2.0 * expected);
         if (cap < p.kk + 64) cap = p.kk + 64;
         cap = (cap + 63) / 64 * 64;

@@ -20,8 +20,11 @@
 // materialised and selected directly, then re-ranked the same way.
 #include <cmath>
 #include <string>
+#include <vector>
 
+#include "autotune.hpp"
 #include "dist.hpp"
+#include "handle.hpp"
 #include "internal.hpp"
 #include "knn.h"
 #include "plan.hpp"
@@ -146,6 +149,39 @@ knn_status_t run_search(knn_handle_t h, const float *Q, int64_t m, const float *
             css = b.css;
         }
     }
+    // tile shape of the fused product: measured once per shape class when
+    // autotuning is on (the timing launches keep nothing: threshold -inf)
+    int ftile = -1;
+    if (autotune_enabled(opt)) {
+        const std::string key = "fused|" + h->arch + "|cu" + std::to_string(num_cu) + "|p" + std::to_string(p.prec) +
+                                "|d" + std::to_string(d) + "|m" + std::to_string(size_bucket(p.Mb)) + "|n" +
+                                std::to_string(size_bucket(n));
+        ftile = autotune_lookup(key);
+        if (ftile < 0) {
+            KNN_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(b.ninf), 1, 0xFF800000u, stream));
+            DistArgs pa{};
+            pa.Q = Q;
+            pa.m = p.Mb < 8192 ? p.Mb : 8192;
+            pa.C = C;
+            pa.n = n;
+            pa.d = d;
+            pa.cnorm = b.cnorm;
+            pa.self_offset = graph ? 0 : -1;
+            pa.tau = b.ninf;
+            pa.tau_stride = 0;
+            pa.cnt = b.cnt;
+            pa.cand = b.cand;
+            pa.cap = p.cap;
+            set_prec(pa, qrow(0), qsrow(0), Cq, csc);
+            std::vector<int> cands = {kTileSmall, kTileWide};
+            if (p.prec != kPrecFP8) cands.push_back(kTileBig);
+            auto run = [&](int t) -> hipError_t {
+                pa.tile = t;
+                return launch_dist_gemm(pa, kEpiFilter, stream);
+            };
+            KNN_TRY(autotune_pick(key, cands, run, stream, 2, &ftile));
+        }
+    }
     uint32_t *hcount = host_counter(h);
     for (int64_t i0 = 0; i0 < m; i0 += p.Mb) {
         const int64_t mb = m - i0 < p.Mb ? m - i0 : p.Mb;
@@ -179,6 +215,7 @@ knn_status_t run_search(knn_handle_t h, const float *Q, int64_t m, const float *
         fa.cnt = b.cnt;
         fa.cand = b.cand;
         fa.cap = p.cap;
+        fa.tile = ftile;
         set_prec(fa, qrow(i0), qsrow(i0), Cq, csc);
         KNN_TRY(timer.begin(stream, 2.0 * (double)mb * (double)n * d));
         KNN_TRY(launch_dist_gemm(fa, kEpiFilter, stream));

@@ -55,6 +55,9 @@ def test_null_handle_rejected_without_launch(lib):
     assert b"handle is null" in lib.knn_last_error(None)
     st = lib.knn_partition(None, None, 1, 1, 1, None, None, None, None, None, None)
     assert st == _abi.KNN_ERROR_INVALID_VALUE
+    jobs = (_abi.Job * 1)()
+    st = lib.knn_batch_search(None, jobs, 1, None, None)
+    assert st == _abi.KNN_ERROR_INVALID_VALUE
     assert lib.knn_destroy(None) == 0
     s = _abi.Stats()
     assert lib.knn_get_stats(None, ctypes.byref(s)) == _abi.KNN_ERROR_INVALID_VALUE
@@ -68,3 +71,9 @@ def test_create_without_gpu_reports_device_error(lib):
     assert lib.knn_create(ctypes.byref(h), 0) == _abi.KNN_ERROR_DEVICE
     assert not h.value
     assert lib.knn_create(None, 0) == _abi.KNN_ERROR_INVALID_VALUE
+
+
+def test_job_struct_layout():
+    # knn_job_t: pointer, int64, pointer, int64, int32, int32, pointer, pointer
+    assert ctypes.sizeof(_abi.Job) == 56
+    assert _abi.Job.d.offset == 32 and _abi.Job.k.offset == 36 and _abi.Job.out_idx.offset == 48

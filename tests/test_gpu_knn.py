@@ -13,9 +13,9 @@ import pytest
 
 import oracle
 import synth
+from knn_check import REL, compare, d64  # noqa: F401
 
 pytestmark = pytest.mark.gpu
-REL = 1e-5
 
 
 def say(*a):
@@ -33,54 +33,6 @@ def torch():
 def h(torch):
     import paper_1309_5478_amd as knn
     return knn.Handle(0)
-
-
-def d64(q, c):
-    diff = q.astype(np.float64) - c.astype(np.float64)
-    return float(np.dot(diff, diff))
-
-
-def compare(Q, C, k, gd, gi, rows, self_ids=None):
-    """Compares GPU rows (gd, gi for the listed query rows) with the oracle.
-    Returns the number of rows whose set differs only inside the near-tie band."""
-    qs = Q[rows]
-    sid = None if self_ids is None else np.asarray(self_ids)[rows]
-    n_elig = C.shape[0] - (0 if sid is None else 1)
-    kk = min(k + 1, n_elig)
-    od, oi = oracle.knn(qs, C, kk, self_ids=sid)
-    near = 0
-    for t, r in enumerate(rows):
-        g_idx = [int(x) for x in gi[t]]
-        assert len(set(g_idx)) == k, f"row {r}: duplicate indices"
-        assert all(0 <= j < C.shape[0] for j in g_idx), f"row {r}: index out of range"
-        if sid is not None:
-            assert int(sid[t]) not in g_idx, f"row {r}: own index returned"
-        # distances against FP64 direct form, for whatever indices were returned
-        for dist, j in zip(gd[t], g_idx):
-            ref = d64(Q[r], C[j])
-            if ref == 0.0:
-                tol = 1e-6 * (d64(Q[r], 0 * Q[r]) + d64(C[j], 0 * C[j]))
-                assert abs(float(dist)) <= tol, (r, j, dist)
-            else:
-                assert abs(float(dist) - ref) <= REL * ref, (r, j, float(dist), ref)
-        # ascending (distance, index)
-        for a in range(k - 1):
-            assert (gd[t, a], g_idx[a]) <= (gd[t, a + 1], g_idx[a + 1]) or gd[t, a] < gd[t, a + 1], (r, a)
-        want = [int(x) for x in oi[t, :k]]
-        if set(g_idx) != set(want):
-            kth = od[t, k - 1]
-            diff = set(g_idx) ^ set(want)
-            band = max(kth, 1e-30) * REL
-            for j in diff:
-                dj = d64(Q[r], C[j])
-                assert abs(dj - kth) <= band, f"row {r}: set differs beyond the near-tie band ({j}: {dj} vs {kth})"
-            near += 1
-        elif g_idx != want:
-            # same set, different order: only legal among FP32-equal distances
-            for a in range(k):
-                if g_idx[a] != want[a]:
-                    assert abs(d64(Q[r], C[g_idx[a]]) - d64(Q[r], C[want[a]])) <= REL * max(od[t, a], 1e-30)
-    return near
 
 
 def run_graph(h, torch, P, k, **kw):
