@@ -83,7 +83,9 @@ typedef struct {
     int32_t flags;      /* KNN_FLAG_* bits                                            */
 } knn_options_t;
 
-/* Force the exact-fallback path of search / graph for every row (tests). */
+/* Force the exact-fallback path of search / graph for every row that takes
+ * the filtering path, i.e. every row of a corpus larger than its threshold
+ * sample (tests). */
 #define KNN_FLAG_FORCE_FALLBACK 0x1
 /* Materialise distance tiles and select from them instead of the fused kernel. */
 #define KNN_FLAG_UNFUSED 0x2

@@ -304,8 +304,8 @@ knn_status_t knn_distances(knn_handle_t h, const float *queries, int64_t m, cons
     float *qn = static_cast<float *>(ws);
     float *cn = qn + ((m + 63) / 64) * 64;
     hipError_t e;
-    if ((e = launch_sqnorm(queries, m, d, qn, stream)) != hipSuccess) return hip_fail(h, e, "norm kernel");
-    if ((e = launch_sqnorm(corpus, n, d, cn, stream)) != hipSuccess) return hip_fail(h, e, "norm kernel");
+    if ((e = launch_sqnorm(queries, m, d, qn, nullptr, stream)) != hipSuccess) return hip_fail(h, e, "norm kernel");
+    if ((e = launch_sqnorm(corpus, n, d, cn, nullptr, stream)) != hipSuccess) return hip_fail(h, e, "norm kernel");
     DistArgs a{};
     a.Q = queries;
     a.m = m;

@@ -19,7 +19,9 @@
 //    of the candidate shapes, timed on the batch itself with a threshold of
 //    -inf (nothing is kept, so the timing run has no effect on the results).
 // Jobs with more than kRowBlock queries are split into parts of at most that
-// many rows; each part has its own candidate lists.
+// many rows; each part has its own candidate lists.  Jobs whose threshold
+// sample is their whole corpus are finished in the first phase, as in
+// knn_search.
 #include <algorithm>
 #include <cstring>
 #include <functional>
@@ -83,6 +85,7 @@ struct BatchJob {
 struct BatchPart {
     int job;
     int64_t i0, mb;
+    bool direct;   // the threshold sample is the whole corpus: its selection is the candidate list
     bool grouped;  // in the grouped launch (else its own launch: FP32 with d % 4 != 0)
     float *tau = nullptr;
     uint32_t *cnt = nullptr;
@@ -238,6 +241,7 @@ size_t carve_batch(Carve &c, BatchState &b, int num_cu, bool probe) {
     }
     for (BatchPart &pt : b.parts) {
         const Plan &p = b.jobs[pt.job].p;
+        if (pt.direct) continue;
         pt.tau = c.take<float>(pt.mb);
         pt.cnt = c.take<uint32_t>(pt.mb);
         pt.cand = c.take<uint64_t>((size_t)pt.mb * p.cap);
@@ -293,7 +297,7 @@ DistArgs part_args(const BatchState &b, const BatchPart &pt) {
 }
 
 // ---- the phases, enqueued on a stream (captured or eager) ------------------
-hipError_t enqueue_prep(const BatchState &b, int num_cu, hipStream_t s) {
+hipError_t enqueue_prep(const BatchState &b, knn_handle_t h, int num_cu, hipStream_t s) {
     hipError_t e = hipSuccess;
     const BatchShared &sh = b.sh;
 #define BTRY(call)                                 \
@@ -304,10 +308,9 @@ hipError_t enqueue_prep(const BatchState &b, int num_cu, hipStream_t s) {
         const BatchJob &js = b.jobs[j];
         const Plan &p = js.p;
         if (js.nparts == 0) continue;
-        BTRY(launch_sqnorm(js.C, js.n, js.d, js.cnorm, s));
-        BTRY(launch_sqnorm(js.Q, js.m, js.d, js.qn2, s));
         BTRY(launch_fill_u32(js.cmax2, 1, 0u, s));
-        BTRY(launch_max_nonneg(js.cnorm, js.n, js.cmax2, s));
+        BTRY(launch_sqnorm(js.C, js.n, js.d, js.cnorm, js.cmax2, s));
+        BTRY(launch_sqnorm(js.Q, js.m, js.d, js.qn2, nullptr, s));
         if (p.prec != kPrecF32) {
             BTRY(launch_quantize(js.C, js.n, js.d, p.prec, js.Cq, js.cs, s));
             if (!js.graph) BTRY(launch_quantize(js.Q, js.m, js.d, p.prec, js.Qq, js.qs, s));
@@ -340,6 +343,15 @@ hipError_t enqueue_prep(const BatchState &b, int num_cu, hipStream_t s) {
             sa.cscale = css;
             BTRY(launch_dist_gemm(sa, kEpiDense, s));
             BTRY(select_dense(sh.Ds, pt.mb, p.S, p.S, p.r + 1, sh.tv, sh.ti, sh.selws, num_cu, b.smode, b.net, s));
+            if (pt.direct) {  // the row's kk smallest keys, in order: certify and re-rank now
+                if (p.kk < p.n_eff)
+                    BTRY(launch_certify(sh.tv, pt.mb, p.kk, js.k, js.qn2 + pt.i0, js.cmax2, p.rel,
+                                        stats_ptr(h) + kStatUncertified, s));
+                RerankArgs rr{js.Q + pt.i0 * js.d, pt.mb, js.C, js.n, js.d, sh.ti, (uint32_t)p.kk, js.k,
+                              js.out_dist + pt.i0 * js.k, js.out_idx + pt.i0 * js.k};
+                BTRY(launch_rerank(rr, s));
+                continue;
+            }
             BTRY(launch_column_copy(sh.tv + p.r, p.r + 1, pt.mb, pt.tau, s));
             BTRY(launch_fill_u32(pt.cnt, pt.mb, 0u, s));
         }
@@ -351,7 +363,7 @@ hipError_t enqueue_product(const BatchState &b, const DistArgs *table, int tile,
     hipError_t e = hipSuccess;
     BTRY(launch_dist_gemm_grouped(table, b.sh.items, (int64_t)b.nitems, b.jobs[0].p.prec, tile, s));
     for (const BatchPart &pt : b.parts) {
-        if (pt.grouped) continue;
+        if (pt.grouped || pt.direct) continue;
         DistArgs fa = part_args(b, pt);
         if (table == b.sh.probe) {
             fa.tau = b.sh.ninf;
@@ -368,6 +380,7 @@ hipError_t enqueue_flags(const BatchState &b, knn_handle_t h, hipStream_t s) {
     for (size_t pi = 0; pi < b.parts.size(); ++pi) {
         const BatchPart &pt = b.parts[pi];
         const Plan &p = b.jobs[pt.job].p;
+        if (pt.direct) continue;
         BTRY(launch_sum_u32(pt.cnt, pt.mb, stats_ptr(h) + kStatCandidates, s));
         BTRY(launch_flag_rows(pt.cnt, pt.mb, (uint32_t)p.kk, (uint32_t)p.cap, b.force, b.sh.nflag + pi, pt.flags, s));
     }
@@ -382,6 +395,7 @@ hipError_t enqueue_final(const BatchState &b, knn_handle_t h, int num_cu, hipStr
         const Plan &p = js.p;
         for (int pi = js.first_part; pi < js.first_part + js.nparts; ++pi) {
             const BatchPart &pt = b.parts[pi];
+            if (pt.direct) continue;
             SelectArgs ka{};
             ka.keys = pt.cand;
             ka.key_cnt = pt.cnt;
@@ -550,7 +564,8 @@ knn_status_t run_batch(knn_handle_t h, const knn_job_t *jobs, int32_t njobs, hip
                 pt.job = j;
                 pt.i0 = i0;
                 pt.mb = jb.m - i0 < js.p.Mb ? jb.m - i0 : js.p.Mb;
-                pt.grouped = !(js.p.prec == kPrecF32 && js.d % 4 != 0);
+                pt.direct = !js.p.gathered;
+                pt.grouped = !pt.direct && !(js.p.prec == kPrecF32 && js.d % 4 != 0);
                 b.parts.push_back(pt);
             }
             js.nparts = (int)b.parts.size() - js.first_part;
@@ -658,13 +673,13 @@ knn_status_t run_batch(knn_handle_t h, const knn_job_t *jobs, int32_t njobs, hip
             hipGraphExec_t g = nullptr;
             bool ok = true;
             if (timed) {
-                ok = capture(b, [&](hipStream_t s) { return enqueue_prep(b, num_cu, s); }, &g) == hipSuccess;
+                ok = capture(b, [&](hipStream_t s) { return enqueue_prep(b, h, num_cu, s); }, &g) == hipSuccess;
                 if (ok) gs.push_back(g);
                 ok = ok && capture(b, [&](hipStream_t s) { return enqueue_flags(b, h, s); }, &g) == hipSuccess;
                 if (ok) gs.push_back(g);
             } else {
                 ok = capture(b, [&](hipStream_t s) {
-                         hipError_t ce = enqueue_prep(b, num_cu, s);
+                         hipError_t ce = enqueue_prep(b, h, num_cu, s);
                          if (ce == hipSuccess) ce = enqueue_product(b, b.sh.table, b.tile, s);
                          if (ce == hipSuccess) ce = enqueue_flags(b, h, s);
                          return ce;
@@ -691,7 +706,7 @@ knn_status_t run_batch(knn_handle_t h, const knn_job_t *jobs, int32_t njobs, hip
     double flops = 0;
     for (const BatchJob &js : b.jobs) flops += js.cost;
     if (b.eager) {
-        KTRY(enqueue_prep(b, num_cu, stream));
+        KTRY(enqueue_prep(b, h, num_cu, stream));
         KTRY(timer.begin(stream, flops));
         KTRY(enqueue_product(b, b.sh.table, b.tile, stream));
         KTRY(timer.end(stream));

@@ -335,18 +335,63 @@ __global__ __launch_bounds__(64 * WM * WN) void dist_gemm_grouped_kernel(const D
     gemm_tile<WM, WN, BI, BJ, EPI, PREC, VEC>(a, w.tm, w.tn, sm);
 }
 
-// ---- squared norms, one wave per point, fixed lane-tree order -------------
+// ---- squared norms ----------------------------------------------------------
+// G lanes per point (the power of two covering the point's 16-byte chunks, or
+// its elements without 16-byte loads; at most 64), 64 / G points per wave,
+// grid-stride over points.  Each lane accumulates its strided elements in
+// order, then a fixed xor-shuffle tree over the G lanes.  With max_bits, the
+// largest norm (as FP32 bits; norms are non-negative) is folded into *max_bits
+// with one atomic per workgroup.
+template <int G, bool VEC>
 __global__ __launch_bounds__(256) void sqnorm_kernel(const float *__restrict__ X, int64_t n, int d,
-                                                     float *__restrict__ out) {
-    const int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.x / kWave;
-    if (i >= n) return;
-    const uint32_t lane = lane_id();
-    const float *x = X + i * d;
-    float s = 0.f;
-    for (int t = lane; t < d; t += kWave) s = fmaf(x[t], x[t], s);
+                                                     float *__restrict__ out, unsigned int *__restrict__ max_bits) {
+    constexpr int PPW = kWave / G;
+    __shared__ float wmax[256 / kWave];
+    const uint32_t lane = lane_id(), sub = lane % G, grp = lane / G, wave = threadIdx.x / kWave;
+    const int64_t stride = (int64_t)gridDim.x * (256 / kWave) * PPW;
+    float mx = 0.f;
+    for (int64_t base = ((int64_t)blockIdx.x * (256 / kWave) + wave) * PPW; base < n; base += stride) {
+        const int64_t i = base + grp;
+        float acc = 0.f;
+        if (i < n) {
+            const float *x = X + i * d;
+            if (VEC) {
+                for (int t = (int)sub * 4; t < d; t += G * 4) {
+                    const f32x4 v = *reinterpret_cast<const f32x4 *>(x + t);
+                    acc = fmaf(v[0], v[0], acc);
+                    acc = fmaf(v[1], v[1], acc);
+                    acc = fmaf(v[2], v[2], acc);
+                    acc = fmaf(v[3], v[3], acc);
+                }
+            } else {
+                for (int t = (int)sub; t < d; t += G) acc = fmaf(x[t], x[t], acc);
+            }
+        }
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    if (lane == 0) out[i] = s;
+        for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        if (i < n && sub == 0) out[i] = acc;
+        mx = fmaxf(mx, acc);
+    }
+    if (max_bits) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+        if (lane == 0) wmax[wave] = mx;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float m = wmax[0];
+            for (int w = 1; w < 256 / kWave; ++w) m = fmaxf(m, wmax[w]);
+            atomicMax(max_bits, __float_as_uint(m));
+        }
+    }
+}
+
+// Lanes per point or candidate for a row length d: the power of two covering
+// its 16-byte chunks (or its elements), at most a wave.
+static int lanes_for(int d, bool vec) {
+    const int units = vec ? (d + 3) / 4 : d;
+    int g = 1;
+    while (g < units && g < kWave) g <<= 1;
+    return g;
 }
 
 // ---- gather rows (and their norms) -----------------------------------------
@@ -395,47 +440,65 @@ __global__ __launch_bounds__(256) void scatter_fallback_kernel(const int32_t *__
 
 // ---- exact re-rank ----------------------------------------------------------
 // One workgroup per query: the exact FP32 squared distance sum_t (q_t - c_t)^2
-// to each of the row's kk candidates (each lane accumulates its strided
-// elements in order, then a fixed xor-shuffle tree), then an LDS bitonic sort
-// of (distance, index) keys; the first k are written.
+// to each of the row's kk candidates, then an LDS bitonic sort of (distance,
+// index) keys; the first k are written (missing entries: +inf, index -1).  G
+// lanes per candidate (the power of two covering d's 16-byte chunks, at most a
+// wave), so a wave works on 64 / G candidates at once, two per lane group per
+// step to keep more loads in flight; each lane accumulates its strided
+// elements in order, then a fixed xor-shuffle tree over the G lanes.
 constexpr int kRerankThreads = 256;
 constexpr int kRerankMax = 1024;
 
-__global__ __launch_bounds__(kRerankThreads) void rerank_kernel(RerankArgs a) {
-    __shared__ uint64_t keys[kRerankMax];
-    const int64_t i = blockIdx.x;
-    if (i >= a.m) return;
-    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
-    const float *q = a.Q + i * a.d;
-    const uint32_t kk = a.kk;
-    const bool vec = (a.d % 4) == 0;
-    for (uint32_t c = wave; c < kk; c += kRerankThreads / kWave) {
-        const uint32_t j = (uint32_t)a.cidx[i * kk + c];
-        if ((int64_t)j >= a.n) {  // a missing candidate (never for valid lists)
-            if (lane == 0) keys[c] = kKeyMax;
-            continue;
-        }
-        const float *y = a.C + (int64_t)j * a.d;
-        float s = 0.f;
-        if (vec) {
-            for (int t = lane * 4; t < a.d; t += kWave * 4) {
-                f32x4 qv = *reinterpret_cast<const f32x4 *>(q + t);
-                f32x4 yv = *reinterpret_cast<const f32x4 *>(y + t);
+template <int G, bool VEC>
+__device__ __forceinline__ float rerank_dist(const float *__restrict__ q, const float *__restrict__ y, int d,
+                                             uint32_t sub) {
+    float s = 0.f;
+    if (VEC) {
+        for (int t = (int)sub * 4; t < d; t += G * 4) {
+            const f32x4 qv = *reinterpret_cast<const f32x4 *>(q + t);
+            const f32x4 yv = *reinterpret_cast<const f32x4 *>(y + t);
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    float df = qv[e] - yv[e];
-                    s = fmaf(df, df, s);
-                }
-            }
-        } else {
-            for (int t = lane; t < a.d; t += kWave) {
-                float df = q[t] - y[t];
+            for (int e = 0; e < 4; ++e) {
+                const float df = qv[e] - yv[e];
                 s = fmaf(df, df, s);
             }
         }
+    } else {
+        for (int t = (int)sub; t < d; t += G) {
+            const float df = q[t] - y[t];
+            s = fmaf(df, df, s);
+        }
+    }
+    return s;
+}
+
+template <int G, bool VEC>
+__global__ __launch_bounds__(kRerankThreads) void rerank_kernel(RerankArgs a) {
+    constexpr uint32_t PPW = kWave / G;                       // candidates per wave per pass
+    constexpr uint32_t STEP = (kRerankThreads / kWave) * PPW;  // per workgroup per pass
+    __shared__ uint64_t keys[kRerankMax];
+    const int64_t i = blockIdx.x;
+    if (i >= a.m) return;
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave, sub = lane % G, grp = lane / G;
+    const float *q = a.Q + i * a.d;
+    const uint32_t kk = a.kk;
+    const int32_t *ci = a.cidx + i * kk;
+    for (uint32_t c0 = wave * PPW + grp; c0 < kk; c0 += 2 * STEP) {
+        const uint32_t c1 = c0 + STEP;
+        const uint32_t j0 = (uint32_t)ci[c0];
+        const uint32_t j1 = c1 < kk ? (uint32_t)ci[c1] : 0xFFFFFFFFu;
+        const bool ok0 = (int64_t)j0 < a.n, ok1 = (int64_t)j1 < a.n;  // missing candidates: never for valid lists
+        float s0 = ok0 ? rerank_dist<G, VEC>(q, a.C + (int64_t)j0 * a.d, a.d, sub) : 0.f;
+        float s1 = ok1 ? rerank_dist<G, VEC>(q, a.C + (int64_t)j1 * a.d, a.d, sub) : 0.f;
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-        if (lane == 0) keys[c] = make_key(s, j);
+        for (int off = G / 2; off > 0; off >>= 1) {
+            s0 += __shfl_xor(s0, off);
+            s1 += __shfl_xor(s1, off);
+        }
+        if (sub == 0) {
+            keys[c0] = ok0 ? make_key(s0, j0) : kKeyMax;
+            if (c1 < kk) keys[c1] = ok1 ? make_key(s1, j1) : kKeyMax;
+        }
     }
     const uint32_t kp2 = next_pow2(kk);
     for (uint32_t t = kk + tid; t < kp2; t += kRerankThreads) keys[t] = kKeyMax;
@@ -509,15 +572,6 @@ __global__ __launch_bounds__(256) void quantize_kernel(const float *__restrict__
 }
 
 // Largest value of a non-negative array into *out (float bits compare as ints).
-__global__ __launch_bounds__(256) void max_nonneg_kernel(const float *__restrict__ x, int64_t n,
-                                                         unsigned int *__restrict__ out) {
-    float m = 0.f;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) m = fmaxf(m, x[i]);
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
-    if (lane_id() == 0) atomicMax(out, __float_as_uint(m));
-}
-
 // A row's kk candidates are certified to contain its true k nearest when the
 // gap between the kk-th and the k-th candidate key exceeds twice the key error
 // bound E_i = 2 rel ||q_i|| max_j ||c_j|| (Cauchy-Schwarz on the dot-product
@@ -638,9 +692,32 @@ hipError_t launch_dist_gemm_grouped(const DistArgs *jobs, const GemmItem *items,
     }
 }
 
-hipError_t launch_sqnorm(const float *X, int64_t n, int d, float *out, hipStream_t stream) {
+template <int G>
+static void launch_sqnorm_g(const float *X, int64_t n, int d, float *out, unsigned int *max_bits, bool vec,
+                            hipStream_t stream) {
+    constexpr int PPW = kWave / G;
+    int64_t blocks = (n + 4 * PPW - 1) / (4 * PPW);
+    if (blocks > 4096) blocks = 4096;
+    if (vec)
+        hipLaunchKernelGGL((sqnorm_kernel<G, true>), dim3((unsigned)blocks), dim3(256), 0, stream, X, n, d, out,
+                           max_bits);
+    else
+        hipLaunchKernelGGL((sqnorm_kernel<G, false>), dim3((unsigned)blocks), dim3(256), 0, stream, X, n, d, out,
+                           max_bits);
+}
+
+hipError_t launch_sqnorm(const float *X, int64_t n, int d, float *out, unsigned int *max_bits, hipStream_t stream) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(sqnorm_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, stream, X, n, d, out);
+    const bool vec = d % 4 == 0 && (reinterpret_cast<uintptr_t>(X) & 15u) == 0;
+    switch (lanes_for(d, vec)) {
+        case 1: launch_sqnorm_g<1>(X, n, d, out, max_bits, vec, stream); break;
+        case 2: launch_sqnorm_g<2>(X, n, d, out, max_bits, vec, stream); break;
+        case 4: launch_sqnorm_g<4>(X, n, d, out, max_bits, vec, stream); break;
+        case 8: launch_sqnorm_g<8>(X, n, d, out, max_bits, vec, stream); break;
+        case 16: launch_sqnorm_g<16>(X, n, d, out, max_bits, vec, stream); break;
+        case 32: launch_sqnorm_g<32>(X, n, d, out, max_bits, vec, stream); break;
+        default: launch_sqnorm_g<64>(X, n, d, out, max_bits, vec, stream); break;
+    }
     return hipGetLastError();
 }
 
@@ -677,14 +754,6 @@ hipError_t launch_quantize(const float *X, int64_t n, int d, int prec, void *out
     return hipGetLastError();
 }
 
-hipError_t launch_max_nonneg(const float *x, int64_t n, unsigned int *out, hipStream_t stream) {
-    int64_t blocks = (n + 255) / 256;
-    if (blocks > 1024) blocks = 1024;
-    if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(max_nonneg_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, x, n, out);
-    return hipGetLastError();
-}
-
 hipError_t launch_certify(const float *sorted_keys, int64_t m, int kk, int k, const float *qnorm2,
                           const unsigned int *cmax2_bits, float rel, unsigned long long *count, hipStream_t stream) {
     if (m == 0) return hipSuccess;
@@ -693,10 +762,28 @@ hipError_t launch_certify(const float *sorted_keys, int64_t m, int kk, int k, co
     return hipGetLastError();
 }
 
+template <int G>
+static void launch_rerank_g(const RerankArgs &a, bool vec, hipStream_t stream) {
+    if (vec)
+        hipLaunchKernelGGL((rerank_kernel<G, true>), dim3((unsigned)a.m), dim3(kRerankThreads), 0, stream, a);
+    else
+        hipLaunchKernelGGL((rerank_kernel<G, false>), dim3((unsigned)a.m), dim3(kRerankThreads), 0, stream, a);
+}
+
 hipError_t launch_rerank(const RerankArgs &a, hipStream_t stream) {
     if (a.m == 0) return hipSuccess;
     if (a.kk > kRerankMax) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(rerank_kernel, dim3((unsigned)a.m), dim3(kRerankThreads), 0, stream, a);
+    const bool vec = a.d % 4 == 0 && (reinterpret_cast<uintptr_t>(a.Q) & 15u) == 0 &&
+                     (reinterpret_cast<uintptr_t>(a.C) & 15u) == 0;
+    switch (lanes_for(a.d, vec)) {
+        case 1: launch_rerank_g<1>(a, vec, stream); break;
+        case 2: launch_rerank_g<2>(a, vec, stream); break;
+        case 4: launch_rerank_g<4>(a, vec, stream); break;
+        case 8: launch_rerank_g<8>(a, vec, stream); break;
+        case 16: launch_rerank_g<16>(a, vec, stream); break;
+        case 32: launch_rerank_g<32>(a, vec, stream); break;
+        default: launch_rerank_g<64>(a, vec, stream); break;
+    }
     return hipGetLastError();
 }
 

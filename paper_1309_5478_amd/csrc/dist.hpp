@@ -78,7 +78,9 @@ hipError_t launch_dist_gemm_grouped(const DistArgs *jobs, const GemmItem *items,
                                     hipStream_t stream);
 // Tile shape launch_dist_gemm uses for `a` (kTile*).
 int gemm_tile_choice(const DistArgs &a);
-hipError_t launch_sqnorm(const float *X, int64_t n, int d, float *out, hipStream_t stream);
+// Squared norms of n rows of d floats into out; with max_bits (non-null, zero or
+// a smaller value at launch) the largest norm's FP32 bits are folded in too.
+hipError_t launch_sqnorm(const float *X, int64_t n, int d, float *out, unsigned int *max_bits, hipStream_t stream);
 hipError_t launch_gather_rows(const float *src, int64_t n, int d, const int32_t *idx, int64_t rows, float *dst,
                               const float *norms, float *dst_norms, hipStream_t stream);
 hipError_t launch_flag_rows(const uint32_t *cnt, int64_t m, uint32_t need, uint32_t cap, int force, uint32_t *nflag,
@@ -96,8 +98,5 @@ hipError_t launch_quantize(const float *X, int64_t n, int d, int prec, void *out
 // error, 2 rel ||q_i|| max_j ||c_j||; uncertified rows are counted into *count.
 hipError_t launch_certify(const float *sorted_keys, int64_t m, int kk, int k, const float *qnorm2,
                           const unsigned int *cmax2_bits, float rel, unsigned long long *count, hipStream_t stream);
-// Largest value of a non-negative FP32 array, as float bits, atomically into *out
-// (which must start at 0).
-hipError_t launch_max_nonneg(const float *x, int64_t n, unsigned int *out, hipStream_t stream);
 
 }  // namespace knn

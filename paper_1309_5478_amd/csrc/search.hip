@@ -16,6 +16,8 @@
 //  4. quick multi-select of the kk smallest reduced keys among each row's
 //     candidates, then the exact FP32 direct-form re-rank of those kk and the
 //     final k, in (distance, index) order.
+// When the sample is the whole corpus (small corpora), step 1 already selects
+// each row's kk smallest keys and steps 2-3 are skipped.
 // Unfused path (KNN_FLAG_UNFUSED): blocks of the distance matrix are
 // materialised and selected directly, then re-ranked the same way.
 #include <cmath>
@@ -68,10 +70,9 @@ knn_status_t run_search(knn_handle_t h, const float *Q, int64_t m, const float *
                                                                                  hipGetErrorString(e)); \
     } while (0)
 
-    KNN_TRY(launch_sqnorm(C, n, d, b.cnorm, stream));
-    KNN_TRY(launch_sqnorm(Q, m, d, b.qn2, stream));
     KNN_TRY(launch_fill_u32(b.cmax2, 1, 0u, stream));
-    KNN_TRY(launch_max_nonneg(b.cnorm, n, b.cmax2, stream));
+    KNN_TRY(launch_sqnorm(C, n, d, b.cnorm, b.cmax2, stream));
+    KNN_TRY(launch_sqnorm(Q, m, d, b.qn2, nullptr, stream));
     const void *Qq = nullptr, *Cq = nullptr;
     const float *qsc = nullptr, *csc = nullptr;
     if (p.prec != kPrecF32) {
@@ -198,8 +199,25 @@ knn_status_t run_search(knn_handle_t h, const float *Q, int64_t m, const float *
         sa.out = b.Ds;
         sa.ldo = p.S;
         set_prec(sa, qrow(i0), qsrow(i0), Csq, css);
+        if (!p.gathered) KNN_TRY(timer.begin(stream, 2.0 * (double)mb * (double)n * d));
         KNN_TRY(launch_dist_gemm(sa, kEpiDense, stream));
+        if (!p.gathered) KNN_TRY(timer.end(stream));
         KNN_TRY(select_dense(b.Ds, mb, p.S, p.S, p.r + 1, b.tv, b.ti, b.selws, num_cu, smode, net, stream));
+        if (!p.gathered) {
+            // the sample is the whole corpus: its selection already holds each
+            // row's kk smallest keys, in order, so the filtered product, the
+            // candidate lists and their selection would only repeat it
+            if (certify)
+                KNN_TRY(launch_certify(b.tv, mb, p.kk, k, b.qn2 + i0, b.cmax2, p.rel, stats_ptr(h) + kStatUncertified,
+                                       stream));
+            RerankArgs rr{Qb, mb, C, n, d, b.ti, (uint32_t)p.kk, k, out_dist + i0 * k, out_idx + i0 * k};
+            KNN_TRY(launch_rerank(rr, stream));
+            if (timer.on) {
+                KNN_TRY(hipStreamSynchronize(stream));
+                KNN_TRY(timer.collect(h));
+            }
+            continue;
+        }
         // 2. fused product + filter
         KNN_TRY(launch_fill_u32(b.cnt, mb, 0u, stream));
         DistArgs fa{};

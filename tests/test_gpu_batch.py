@@ -166,7 +166,11 @@ def test_batch_forced_fallback_and_unfused(h, knn, torch, data):
     forced = h.batch_search(jobs, flags=knn.FLAG_FORCE_FALLBACK)
     torch.cuda.synchronize()
     st = h.stats()
-    assert st["fallback_rows"] == sum(j["m"] for j in data)
+    # every row on the filtering path is re-done; corpora of at most 2048 points
+    # are their own threshold sample and never filter, corpora above 16384
+    # points always do
+    assert sum(j["m"] for j in data if j["n"] > 16384) <= st["fallback_rows"]
+    assert st["fallback_rows"] <= sum(j["m"] for j in data if j["n"] > 2048)
     assert_same(forced, base, "forced fallback")
     unf = h.batch_search(jobs, flags=knn.FLAG_UNFUSED)
     torch.cuda.synchronize()
