@@ -441,11 +441,11 @@ __global__ __launch_bounds__(256) void scatter_fallback_kernel(const int32_t *__
 // ---- exact re-rank ----------------------------------------------------------
 // One workgroup per query: the exact FP32 squared distance sum_t (q_t - c_t)^2
 // to each of the row's kk candidates, then an LDS bitonic sort of (distance,
-// index) keys; the first k are written (missing entries: +inf, index -1).  G
-// lanes per candidate (the power of two covering d's 16-byte chunks, at most a
-// wave), so a wave works on 64 / G candidates at once, two per lane group per
-// step to keep more loads in flight; each lane accumulates its strided
-// elements in order, then a fixed xor-shuffle tree over the G lanes.
+// index) keys; the first k are written (missing entries: +inf, index -1).
+// G lanes per candidate (the power of two covering d's 16-byte chunks, at
+// most a wave), so a wave works on 64 / G candidates at once, two per lane
+// group per step to keep more loads in flight; each lane accumulates its
+// strided elements in order, then a fixed xor-shuffle tree over the G lanes.
 constexpr int kRerankThreads = 256;
 constexpr int kRerankMax = 1024;
 

@@ -41,6 +41,7 @@ constexpr int kSortN = 1024;        // sample size; also the largest k
 constexpr int kSampleBlocks = kSortN / kWave;
 constexpr int kStackDepth = 64;
 constexpr int kMaxPasses = 4096;    // hard bound; unreachable with distinct keys
+constexpr int kAccSlots = 10;       // per-workgroup statistics totals
 
 template <int CAP>
 struct SelSmem {
@@ -53,6 +54,7 @@ struct SelSmem {
     uint64_t pivot;
     uint32_t cnt_lt;
     uint32_t cnt_ge;
+    unsigned long long acc[kAccSlots];
 };
 
 // The two partition buffers: positions below CAP live in LDS, the rest in a
@@ -337,9 +339,11 @@ __device__ __forceinline__ uint64_t merge_rank(SelSmem<CAP> &sm, uint32_t r) {
     return mn;
 }
 
+// The CAP = 1024 instance (k <= 64) is held to 128 registers so that four
+// workgroups share a CU (its LDS allows it); the others are limited by LDS.
 template <int CAP, bool KEYS>
-__global__ __launch_bounds__(kSelThreads) void select_rows_kernel(SelectArgs a, uint64_t *ws,
-                                                                   uint64_t ws_slot) {
+__global__ __launch_bounds__(kSelThreads, (CAP == 1024 && !KEYS) ? 4 : 1) void select_rows_kernel(
+    SelectArgs a, uint64_t *ws, uint64_t ws_slot) {
     __shared__ SelSmem<CAP> sm;
     static_assert(sizeof(sm.buf) >= (size_t)(kNetParams + 1) * 2, "partition buffers must hold the pivot network");
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
@@ -347,6 +351,9 @@ __global__ __launch_bounds__(kSelThreads) void select_rows_kernel(SelectArgs a, 
     GBuf gb{ws + (uint64_t)blockIdx.x * 2 * ws_slot, ws + (uint64_t)blockIdx.x * 2 * ws_slot + ws_slot};
     const bool vec = ((reinterpret_cast<uintptr_t>(a.dist) & 15u) == 0) && ((a.ld & 3) == 0);
 
+    // per-workgroup totals of the row statistics, in LDS (kept by thread 0)
+    if (tid < kAccSlots) sm.acc[tid] = 0;
+    __syncthreads();
     for (int64_t r = blockIdx.x; r < a.rows; r += gridDim.x) {
         const float *row = a.dist + r * a.ld;
         uint32_t nstack = 0, agg = 0, passes = 0, stream_passes = 0, spill = 0, first = 0;
@@ -569,19 +576,33 @@ __global__ __launch_bounds__(kSelThreads) void select_rows_kernel(SelectArgs a, 
             for (uint32_t t = tid; t < k; t += kSelThreads) emit(t, sm.sortbuf[t]);
         }
         long long t4 = clock64();
-        if (tid == 0 && a.stats) {
-            atomicAdd(&a.stats[kStatRows], 1ull);
-            atomicAdd(&a.stats[kStatPasses], (unsigned long long)passes);
-            atomicMax(&a.stats[kStatPassesMax], (unsigned long long)passes);
-            atomicAdd(&a.stats[kStatStreamPasses], (unsigned long long)stream_passes);
-            atomicAdd(&a.stats[kStatSpillRows], (unsigned long long)spill);
-            atomicAdd(&a.stats[kStatFirstSurvivors], (unsigned long long)first);
-            atomicAdd(&a.stats[kStatCycSample], (unsigned long long)cyc_sample);
-            atomicAdd(&a.stats[kStatCycStream], (unsigned long long)cyc_stream);
-            atomicAdd(&a.stats[kStatCycSelect], (unsigned long long)(t3 - t2));
-            atomicAdd(&a.stats[kStatCycFinal], (unsigned long long)(t4 - t3));
+        // per-workgroup totals, published once after the last row (all rows'
+        // counters share one cache line: per-row atomics would serialise there)
+        if (tid == 0) {
+            sm.acc[0] += 1;
+            sm.acc[1] += passes;
+            sm.acc[2] = passes > sm.acc[2] ? passes : sm.acc[2];
+            sm.acc[3] += stream_passes;
+            sm.acc[4] += spill;
+            sm.acc[5] += first;
+            sm.acc[6] += (unsigned long long)cyc_sample;
+            sm.acc[7] += (unsigned long long)cyc_stream;
+            sm.acc[8] += (unsigned long long)(t3 - t2);
+            sm.acc[9] += (unsigned long long)(t4 - t3);
         }
         __syncthreads();
+    }
+    if (tid == 0 && a.stats && sm.acc[0]) {
+        atomicAdd(&a.stats[kStatRows], sm.acc[0]);
+        atomicAdd(&a.stats[kStatPasses], sm.acc[1]);
+        atomicMax(&a.stats[kStatPassesMax], sm.acc[2]);
+        atomicAdd(&a.stats[kStatStreamPasses], sm.acc[3]);
+        atomicAdd(&a.stats[kStatSpillRows], sm.acc[4]);
+        atomicAdd(&a.stats[kStatFirstSurvivors], sm.acc[5]);
+        atomicAdd(&a.stats[kStatCycSample], sm.acc[6]);
+        atomicAdd(&a.stats[kStatCycStream], sm.acc[7]);
+        atomicAdd(&a.stats[kStatCycSelect], sm.acc[8]);
+        atomicAdd(&a.stats[kStatCycFinal], sm.acc[9]);
     }
 }
 
