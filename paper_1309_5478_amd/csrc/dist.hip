@@ -440,7 +440,7 @@ __global__ __launch_bounds__(256) void scatter_fallback_kernel(const int32_t *__
 
 // ---- exact re-rank ----------------------------------------------------------
 // One workgroup per query: the exact FP32 squared distance sum_t (q_t - c_t)^2
-// to each of the row's kk candidates, then an LDS bitonic sort of (distance,
+// to each of the row's kk candidates, then a bitonic sort of the (distance,
 // index) keys; the first k are written (missing entries: +inf, index -1).
 // G lanes per candidate (the power of two covering d's 16-byte chunks, at
 // most a wave), so a wave works on 64 / G candidates at once, two per lane
@@ -500,10 +500,8 @@ __global__ __launch_bounds__(kRerankThreads) void rerank_kernel(RerankArgs a) {
             if (c1 < kk) keys[c1] = ok1 ? make_key(s1, j1) : kKeyMax;
         }
     }
-    const uint32_t kp2 = next_pow2(kk);
-    for (uint32_t t = kk + tid; t < kp2; t += kRerankThreads) keys[t] = kKeyMax;
     __syncthreads();
-    block_bitonic_sort<kRerankThreads>(keys, kp2);
+    block_sort<kRerankThreads>(keys, kk);
     for (uint32_t t = tid; t < (uint32_t)a.k; t += kRerankThreads) {
         const uint64_t key = t < kk ? keys[t] : kKeyMax;
         if (key == kKeyMax) {

@@ -105,30 +105,86 @@ __device__ __forceinline__ uint64_t wave_readlane_u64(uint64_t v, int lane) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-// Ascending bitonic sort of n (a power of two) keys in LDS by the whole block.
-template <int NT>
-__device__ __forceinline__ void block_bitonic_sort(uint64_t *buf, uint32_t n) {
-    for (uint32_t size = 2; size <= n; size <<= 1) {
+// Ascending bitonic sort of NT * J keys of buf (J = 1, 2 or 4), with the keys
+// in registers: thread t holds keys t*J .. t*J + J - 1, so compare-exchange
+// partners less than J apart are in the same thread, partners less than 64*J
+// apart are in the same wave (one shuffle), and only the strides of J*64 and
+// above go through LDS, with a barrier each.
+template <int NT, int J>
+__device__ __forceinline__ void block_sort_regs(uint64_t *buf) {
+    constexpr uint32_t N = (uint32_t)NT * J;
+    const uint32_t t = threadIdx.x;
+    uint64_t k[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) k[j] = buf[t * J + j];
+    auto cas = [](uint64_t &lo, uint64_t &hi, bool up) {
+        const uint64_t a = lo, b = hi;
+        const bool swap = (a > b) == up;
+        lo = swap ? b : a;
+        hi = swap ? a : b;
+    };
+#pragma unroll 1
+    for (uint32_t size = 2; size <= N; size <<= 1) {
+#pragma unroll 1
         for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-            for (uint32_t i = threadIdx.x; i < (n >> 1); i += NT) {
-                uint32_t lo = 2 * i - (i & (stride - 1));
-                uint32_t hi = lo + stride;
-                bool up = (lo & size) == 0;
-                uint64_t a = buf[lo], b = buf[hi];
-                if ((a > b) == up) {
-                    buf[lo] = b;
-                    buf[hi] = a;
+            if (stride < (uint32_t)J) {
+                if constexpr (J >= 2) {
+                    if (stride == 1) {
+#pragma unroll
+                        for (int j = 0; j < J; j += 2) cas(k[j], k[j + 1], ((t * J + j) & size) == 0);
+                    }
                 }
+                if constexpr (J >= 4) {
+                    if (stride == 2) {
+#pragma unroll
+                        for (int j = 0; j < 2; ++j) cas(k[j], k[j + 2], ((t * J + j) & size) == 0);
+                    }
+                }
+            } else if (stride < (uint32_t)J * kWave) {
+                const int ls = (int)(stride / J);
+#pragma unroll
+                for (int j = 0; j < J; ++j) {
+                    const uint32_t i = t * J + j;
+                    const uint64_t o = shfl_xor_u64(k[j], ls);
+                    const bool take_min = ((i & stride) == 0) == ((i & size) == 0);
+                    const uint64_t mn = k[j] < o ? k[j] : o, mx = k[j] < o ? o : k[j];
+                    k[j] = take_min ? mn : mx;
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < J; ++j) buf[t * J + j] = k[j];
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < J; ++j) {
+                    const uint32_t i = t * J + j;
+                    const uint64_t o = buf[i ^ stride];
+                    const bool take_min = ((i & stride) == 0) == ((i & size) == 0);
+                    const uint64_t mn = k[j] < o ? k[j] : o, mx = k[j] < o ? o : k[j];
+                    k[j] = take_min ? mn : mx;
+                }
+                __syncthreads();
             }
-            __syncthreads();
         }
     }
+#pragma unroll
+    for (int j = 0; j < J; ++j) buf[t * J + j] = k[j];
+    __syncthreads();
 }
 
-__device__ __forceinline__ uint32_t next_pow2(uint32_t x) {
-    uint32_t p = 1;
-    while (p < x) p <<= 1;
-    return p;
+// Ascending sort of the first n keys of buf (n <= 4 * NT): pads to NT, 2 NT or
+// 4 NT keys with the largest key, then sorts in registers (the buffer must
+// hold the padded length).  Callers have made the n keys visible (barrier).
+template <int NT>
+__device__ __forceinline__ void block_sort(uint64_t *buf, uint32_t n) {
+    const uint32_t m = n <= (uint32_t)NT ? NT : (n <= 2u * NT ? 2 * NT : 4 * NT);
+    for (uint32_t t = n + threadIdx.x; t < m; t += NT) buf[t] = kKeyMax;
+    __syncthreads();
+    if (m == (uint32_t)NT)
+        block_sort_regs<NT, 1>(buf);
+    else if (m == 2u * NT)
+        block_sort_regs<NT, 2>(buf);
+    else
+        block_sort_regs<NT, 4>(buf);
 }
 
 }  // namespace knn

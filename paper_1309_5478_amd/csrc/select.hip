@@ -429,7 +429,7 @@ __global__ __launch_bounds__(kSelThreads, (CAP == 1024 && !KEYS) ? 4 : 1) void s
                         __syncthreads();
                         P = sm.pivot;
                     } else {
-                        block_bitonic_sort<kSelThreads>(sm.sortbuf, kSortN);
+                        block_sort<kSelThreads>(sm.sortbuf, kSortN);
                         sample_sorted = true;
                         P = sm.sortbuf[rr0];
                     }
@@ -475,7 +475,7 @@ __global__ __launch_bounds__(kSelThreads, (CAP == 1024 && !KEYS) ? 4 : 1) void s
                     sample_loaded = true;
                 }
                 if (!sample_sorted) {
-                    block_bitonic_sort<kSelThreads>(sm.sortbuf, kSortN);
+                    block_sort<kSelThreads>(sm.sortbuf, kSortN);
                     sample_sorted = true;
                 }
                 // next pivot: about twice as far into the sample as the old one
@@ -569,10 +569,7 @@ __global__ __launch_bounds__(kSelThreads, (CAP == 1024 && !KEYS) ? 4 : 1) void s
                 if (lane < k) emit(lane, key);
             }
         } else {
-            const uint32_t kp2 = next_pow2(k);
-            for (uint32_t t = agg + tid; t < kp2; t += kSelThreads) sm.sortbuf[t] = kKeyMax;
-            __syncthreads();
-            block_bitonic_sort<kSelThreads>(sm.sortbuf, kp2);
+            block_sort<kSelThreads>(sm.sortbuf, agg);
             for (uint32_t t = tid; t < k; t += kSelThreads) emit(t, sm.sortbuf[t]);
         }
         long long t4 = clock64();
