@@ -67,7 +67,7 @@ def main():
     ap.add_argument("--no-select", action="store_true", help="skip the select_k block")
     ap.add_argument("--no-pivot-compare", action="store_true", help="skip the per-pivot-rule steps")
     ap.add_argument("--cpu-rows", type=int, default=1536, help="query rows in the CPU oracle sample (0: skip)")
-    ap.add_argument("--workload", default="knng", choices=["knng", "batch"])
+    ap.add_argument("--workload", default="knng", choices=["knng", "batch", "select"])
     ap.add_argument("--batch-jobs", type=int, default=512)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference dispatch for memory counters)")
@@ -88,6 +88,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.workload == "batch":
         return bench_batch(args, knn, torch, np)
+    if args.workload == "select":
+        return bench_select(args, knn, torch, np)
     N, d, k = args.n, args.d, args.k
     t0 = time.perf_counter()
     P = synth.gmm_points(N, d, seed=synth.SEEDS["knng_fused"])
@@ -202,6 +204,75 @@ def main():
         "select": select,
         "fallback_rows_per_step": fallback / args.steps,
         "candidates_per_row": round(cands / args.steps / N, 1),
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_select(args, knn, torch, np):
+    import synth
+    M, N, d = 16384, 65536, 256
+    t0 = time.perf_counter()
+    D = synth.sqdist_matrix_normal(M, N, d, seed=synth.SEEDS["select"])
+    log(f"generated {M}x{N} squared-distance matrix in {time.perf_counter() - t0:.1f} s")
+    dev = torch.from_numpy(D).cuda()
+    torch.cuda.synchronize()
+    h = knn.Handle(0)
+    res, tot_bytes, tot_ms = {}, 0.0, 0.0
+    for k in (32, 256, 1024):
+        nbytes = 4 * M * N + 8 * M * k
+        for pivot in ("sample", "learned", "plain"):
+            for _ in range(args.warmup):
+                h.select_k(dev, k, pivot=pivot)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(args.steps):
+                h.select_k(dev, k, pivot=pivot)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+            st = h.stats()
+            res[f"k={k},{pivot}"] = {"ms": round(ms, 4), "GB/s": round(nbytes / ms / 1e6, 1),
+                                     "passes_per_row": round(st["passes_total"] / M, 3),
+                                     "streams_per_row": round(st["stream_passes_total"] / M, 4)}
+            log(f"select_k k={k} pivot={pivot}: {ms:.3f} ms, {nbytes / ms / 1e6:.0f} GB/s")
+            if pivot == "sample":
+                tot_bytes += nbytes
+                tot_ms += ms
+    gbs = tot_bytes / tot_ms / 1e6
+    cpu = None
+    if args.cpu_rows > 0:
+        import oracle
+        rows = np.random.default_rng(0).choice(M, min(args.cpu_rows, 256), replace=False)
+        threads = oracle.default_threads()
+        sec = 0.0
+        for k in (32, 256, 1024):
+            a = time.perf_counter()
+            oracle.select_k(D[rows], k, nthreads=threads)
+            sec += time.perf_counter() - a
+        cpu = {"value": round(3 * len(rows) * 4 * N / sec / 1e9, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
+               "sample": f"{len(rows)} rows of the matrix at each of k = 32, 256, 1024 (stable sort of each row), {sec:.1f} s"}
+        log(f"oracle: {cpu['value']} GB/s on {threads} threads")
+    line = {
+        "metric": "select_k GB/s (16384x65536 FP32 squared distances, k = 32 / 256 / 1024)",
+        "value": round(gbs, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(tot_ms, 4),
+        "higher_is_better": True,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "select_k on 16384 x 65536 FP32 squared distances of N(0,1) points in d = 256,"
+                               " k = 32, 256, 1024, sample pivots (one step = the three k)",
+                   "rows": M, "cols": N},
+        "per_k": res,
+        "roofline": {"bound": "hbm", "kernel": "select_rows_kernel", "achieved": round(gbs, 1),
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
