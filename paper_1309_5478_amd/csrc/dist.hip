@@ -18,6 +18,8 @@
 #include <cstdlib>
 #include <cstring>
 
+#include <type_traits>
+
 #include "dist.hpp"
 #include "keys.hpp"
 
@@ -209,13 +211,17 @@ __device__ __forceinline__ void gemm_tile(const DistArgs &a, uint32_t tm, uint32
     const uint32_t h = lane / 32, l32 = lane % 32;
 
     // per-row thresholds / ids / scales and per-column norms / scales for the epilogue
+    bool self_hit = false;  // some row's own index falls in this tile's columns
     for (uint32_t t = tid; t < (uint32_t)BM; t += NT) {
         uint32_t gi = row0 + t;
         sm.tau[t] = (EPI == kEpiFilter && gi < a.m) ? a.tau[(int64_t)gi * a.tau_stride] : 0.f;
         sm.qn[t] = (a.qnorm && gi < a.m) ? a.qnorm[gi] : 0.f;
         sm.qs[t] = (PREC == kPrecFP8 && gi < a.m) ? a.qscale[gi] : 1.f;
-        sm.qid[t] = (a.self_offset >= 0 && gi < a.m) ? a.self_offset + (a.row_ids ? (int64_t)a.row_ids[gi] : (int64_t)gi)
-                                                     : (int64_t)-1;
+        const int64_t q = (a.self_offset >= 0 && gi < a.m)
+                              ? a.self_offset + (a.row_ids ? (int64_t)a.row_ids[gi] : (int64_t)gi)
+                              : (int64_t)-1;
+        sm.qid[t] = q;
+        self_hit |= q >= (int64_t)col0 && q < (int64_t)col0 + BN;
     }
     for (uint32_t t = tid; t < (uint32_t)BN; t += NT) {
         uint32_t gj = col0 + t;
@@ -233,6 +239,8 @@ __device__ __forceinline__ void gemm_tile(const DistArgs &a, uint32_t tm, uint32
 
     constexpr uint32_t per_chunk = PREC == kPrecF32 ? 32 : (PREC == kPrecBF16 ? 64 : 128);
     const uint32_t nk = ((uint32_t)a.d + per_chunk - 1) / per_chunk;
+    // (also the barrier that publishes the per-row and per-column values)
+    const bool may_self = __syncthreads_or(self_hit) != 0;
     f32x4 ra[A4], rb[B4];
     load_chunk<NT, BM, BN, PREC, VEC>(a, row0, col0, 0, ra, rb);
     store_chunk<NT, BM, BN>(sm, 0, ra, rb);
@@ -249,50 +257,59 @@ __device__ __forceinline__ void gemm_tile(const DistArgs &a, uint32_t tm, uint32
     // epilogue: element (i, j) of block (bi, bj), register r, lane l:
     //   row = r0 + bi*32 + 8*(r/4) + 4*h + r%4, col = c0 + bj*32 + l%32
     // d' = ||c_j||^2 - 2 q_i.c_j, with q_i.c_j = acc * qscale_i * cscale_j (FP8).
-    // Interior tiles with no possible own-index column skip the per-element
-    // bounds and self tests.
-    const bool interior = row0 + BM <= a.m && col0 + BN <= a.n;
-    const bool may_self = a.self_offset >= 0;
+    // Instantiated four ways so that interior tiles skip the bounds tests and
+    // tiles holding no row's own index skip the self test.
+    auto epilogue = [&](auto bounds_t, auto self_t) {
+        constexpr bool BOUNDS = decltype(bounds_t)::value, SELF = decltype(self_t)::value;
 #pragma unroll
-    for (int bi = 0; bi < BI; ++bi) {
+        for (int bi = 0; bi < BI; ++bi) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const uint32_t rl = r0 + bi * 32 + 8 * (r / 4) + 4 * h + (r % 4);
-            const uint32_t gi = row0 + rl;
-            const float tau = EPI == kEpiFilter ? sm.tau[rl] : 0.f;
-            const int64_t qid = sm.qid[rl];
-            const float qs = PREC == kPrecFP8 ? sm.qs[rl] : 1.f;
+            for (int r = 0; r < 16; ++r) {
+                const uint32_t rl = r0 + bi * 32 + 8 * (r / 4) + 4 * h + (r % 4);
+                const uint32_t gi = row0 + rl;
+                const float tau = EPI == kEpiFilter ? sm.tau[rl] : 0.f;
+                const int64_t qid = SELF ? sm.qid[rl] : (int64_t)-1;
+                const float qs = PREC == kPrecFP8 ? sm.qs[rl] : 1.f;
 #pragma unroll
-            for (int bj = 0; bj < BJ; ++bj) {
-                const uint32_t cl = c0 + bj * 32 + l32;
-                const uint32_t gj = col0 + cl;
-                const float cn = sm.cn[cl];
-                const float cs = sm.cs[cl];
-                const float dot = PREC == kPrecFP8 ? acc[bi][bj][r] * qs : acc[bi][bj][r];
-                const float dp = fmaf(cs, dot, cn);
-                const bool in = interior || ((gi < a.m) & (gj < a.n));
-                const bool self = may_self && (int64_t)gj == qid;
-                if (EPI == kEpiDense) {
-                    // with query norms: ||q||^2 + ||c||^2 - 2 q.c; without: the reduced key d'
-                    const float v = a.qnorm ? fmaf(cs, dot, sm.qn[rl] + cn) : dp;
-                    if (in) a.out[(int64_t)gi * a.ldo + gj] = self ? __uint_as_float(0x7f800000u) : v;
-                } else {
-                    const bool pass = in & !self & (dp <= tau);
-                    const uint64_t m = __ballot(pass);
-                    if (m) {
-                        const uint32_t half = h ? (uint32_t)(m >> 32) : (uint32_t)m;
-                        uint32_t v = 0;
-                        if (l32 == 0 && half) v = atomicAdd(&a.cnt[gi], (uint32_t)__popc(half));
-                        const uint32_t b0 = __shfl(v, 0), b1 = __shfl(v, 32);
-                        if (pass) {
-                            const uint32_t below = lanes_below(m) - (h ? (uint32_t)__popc((uint32_t)m) : 0u);
-                            const uint32_t slot = (h ? b1 : b0) + below;
-                            if (slot < (uint32_t)a.cap) a.cand[(int64_t)gi * a.cap + slot] = make_key(dp, gj);
+                for (int bj = 0; bj < BJ; ++bj) {
+                    const uint32_t cl = c0 + bj * 32 + l32;
+                    const uint32_t gj = col0 + cl;
+                    const float cn = sm.cn[cl];
+                    const float cs = sm.cs[cl];
+                    const float dot = PREC == kPrecFP8 ? acc[bi][bj][r] * qs : acc[bi][bj][r];
+                    const float dp = fmaf(cs, dot, cn);
+                    const bool in = !BOUNDS || ((gi < a.m) & (gj < a.n));
+                    const bool self = SELF && (int64_t)gj == qid;
+                    if (EPI == kEpiDense) {
+                        // with query norms: ||q||^2 + ||c||^2 - 2 q.c; without: the reduced key d'
+                        const float v = a.qnorm ? fmaf(cs, dot, sm.qn[rl] + cn) : dp;
+                        if (in) a.out[(int64_t)gi * a.ldo + gj] = self ? __uint_as_float(0x7f800000u) : v;
+                    } else {
+                        const bool pass = in & !self & (dp <= tau);
+                        const uint64_t m = __ballot(pass);
+                        if (m) {
+                            const uint32_t half = h ? (uint32_t)(m >> 32) : (uint32_t)m;
+                            uint32_t v = 0;
+                            if (l32 == 0 && half) v = atomicAdd(&a.cnt[gi], (uint32_t)__popc(half));
+                            const uint32_t b0 = __shfl(v, 0), b1 = __shfl(v, 32);
+                            if (pass) {
+                                const uint32_t below = lanes_below(m) - (h ? (uint32_t)__popc((uint32_t)m) : 0u);
+                                const uint32_t slot = (h ? b1 : b0) + below;
+                                if (slot < (uint32_t)a.cap) a.cand[(int64_t)gi * a.cap + slot] = make_key(dp, gj);
+                            }
                         }
                     }
                 }
             }
         }
+    };
+    const bool interior = row0 + BM <= a.m && col0 + BN <= a.n;
+    if (interior) {
+        if (may_self) epilogue(std::false_type{}, std::true_type{});
+        else epilogue(std::false_type{}, std::false_type{});
+    } else {
+        if (may_self) epilogue(std::true_type{}, std::true_type{});
+        else epilogue(std::true_type{}, std::false_type{});
     }
 }
 
