@@ -39,10 +39,10 @@ struct Tile {
     static constexpr int BN = 32 * BJ * WN;
 };
 
-template <int BM, int BN>
+template <int BM, int BN, int ST>
 struct GemmSmem {
-    float A[2][BM][kLdsStride];
-    float B[2][BN][kLdsStride];
+    float A[ST][BM][kLdsStride];  // ST operand stages (2: double-buffered)
+    float B[ST][BN][kLdsStride];
     float tau[BM];
     int64_t qid[BM];  // global id of each query row (self exclusion), -1 if none
     float qn[BM];
@@ -107,8 +107,8 @@ __device__ __forceinline__ void load_chunk(const DistArgs &a, uint32_t row0, uin
     }
 }
 
-template <int NT, int BM, int BN>
-__device__ __forceinline__ void store_chunk(GemmSmem<BM, BN> &sm, int buf, const f32x4 *ra, const f32x4 *rb) {
+template <int NT, int BM, int BN, int ST>
+__device__ __forceinline__ void store_chunk(GemmSmem<BM, BN, ST> &sm, int buf, const f32x4 *ra, const f32x4 *rb) {
     constexpr int A4 = BM * 8 / NT;
     constexpr int B4 = BN * 8 / NT;
     const uint32_t tid = threadIdx.x;
@@ -135,8 +135,8 @@ typedef int i32x8 __attribute__((ext_vector_type(8)));
 //  FP8:  2 steps of 64 k; two 16-byte reads per operand per
 //        v_mfma_scale_f32_32x32x64_f8f6f4 with OCP e4m3 operands and unit scales
 //        (lane half h holds k = 64s + 32h .. +31).
-template <int BM, int BN, int BI, int BJ, int PREC>
-__device__ __forceinline__ void mma_chunk(GemmSmem<BM, BN> &sm, int cur, uint32_t r0, uint32_t c0, uint32_t h,
+template <int BM, int BN, int BI, int BJ, int PREC, int ST>
+__device__ __forceinline__ void mma_chunk(GemmSmem<BM, BN, ST> &sm, int cur, uint32_t r0, uint32_t c0, uint32_t h,
                                           uint32_t l32, f32x16 (&acc)[BI][BJ]) {
     if (PREC == kPrecF32) {
 #pragma unroll
@@ -196,9 +196,9 @@ __device__ __forceinline__ void mma_chunk(GemmSmem<BM, BN> &sm, int cur, uint32_
 
 // One output tile (tm, tn) of one product: staged K loop on the matrix cores,
 // then the dense or filter epilogue.  Called by every thread of the workgroup.
-template <int WM, int WN, int BI, int BJ, int EPI, int PREC, bool VEC>
+template <int WM, int WN, int BI, int BJ, int EPI, int PREC, bool VEC, int ST>
 __device__ __forceinline__ void gemm_tile(const DistArgs &a, uint32_t tm, uint32_t tn,
-                                          GemmSmem<Tile<WM, WN, BI, BJ>::BM, Tile<WM, WN, BI, BJ>::BN> &sm) {
+                                          GemmSmem<Tile<WM, WN, BI, BJ>::BM, Tile<WM, WN, BI, BJ>::BN, ST> &sm) {
     using T = Tile<WM, WN, BI, BJ>;
     constexpr int NT = T::NT, BM = T::BM, BN = T::BN;
     constexpr int A4 = BM * 8 / NT;
@@ -243,14 +243,18 @@ __device__ __forceinline__ void gemm_tile(const DistArgs &a, uint32_t tm, uint32
     const bool may_self = __syncthreads_or(self_hit) != 0;
     f32x4 ra[A4], rb[B4];
     load_chunk<NT, BM, BN, PREC, VEC>(a, row0, col0, 0, ra, rb);
-    store_chunk<NT, BM, BN>(sm, 0, ra, rb);
+    store_chunk<NT, BM, BN, ST>(sm, 0, ra, rb);
     __syncthreads();
 
+    // two stages: the next chunk goes to the other buffer while this one is
+    // consumed; one stage (half the LDS, so more workgroups per CU): it waits
+    // in registers until every wave is done with the buffer
     for (uint32_t kc = 0; kc < nk; ++kc) {
-        const int cur = kc & 1;
+        const int cur = ST == 2 ? (int)(kc & 1) : 0;
         if (kc + 1 < nk) load_chunk<NT, BM, BN, PREC, VEC>(a, row0, col0, kc + 1, ra, rb);
-        mma_chunk<BM, BN, BI, BJ, PREC>(sm, cur, r0, c0, h, l32, acc);
-        if (kc + 1 < nk) store_chunk<NT, BM, BN>(sm, cur ^ 1, ra, rb);
+        mma_chunk<BM, BN, BI, BJ, PREC, ST>(sm, cur, r0, c0, h, l32, acc);
+        if (ST == 1 && kc + 1 < nk) __syncthreads();
+        if (kc + 1 < nk) store_chunk<NT, BM, BN, ST>(sm, ST == 2 ? cur ^ 1 : 0, ra, rb);
         __syncthreads();
     }
 
@@ -313,15 +317,15 @@ __device__ __forceinline__ void gemm_tile(const DistArgs &a, uint32_t tm, uint32
     }
 }
 
-template <int WM, int WN, int BI, int BJ, int EPI, int PREC, bool VEC>
+template <int WM, int WN, int BI, int BJ, int EPI, int PREC, bool VEC, int ST>
 __global__ __launch_bounds__(64 * WM * WN) void dist_gemm_kernel(DistArgs a) {
     using T = Tile<WM, WN, BI, BJ>;
-    __shared__ GemmSmem<T::BM, T::BN> sm;
+    __shared__ GemmSmem<T::BM, T::BN, ST> sm;
     uint32_t tm, tn;
     bool valid;
     tile_of_block(blockIdx.x, a.tiles_m, a.tiles_n, tm, tn, valid);
     if (!valid) return;  // whole workgroup leaves together
-    gemm_tile<WM, WN, BI, BJ, EPI, PREC, VEC>(a, tm, tn, sm);
+    gemm_tile<WM, WN, BI, BJ, EPI, PREC, VEC, ST>(a, tm, tn, sm);
 }
 
 // A structure at an address that is the same in every lane, held in scalar
@@ -346,10 +350,10 @@ template <int WM, int WN, int BI, int BJ, int EPI, int PREC, bool VEC>
 __global__ __launch_bounds__(64 * WM * WN) void dist_gemm_grouped_kernel(const DistArgs *__restrict__ jobs,
                                                                          const GemmItem *__restrict__ items) {
     using T = Tile<WM, WN, BI, BJ>;
-    __shared__ GemmSmem<T::BM, T::BN> sm;
+    __shared__ GemmSmem<T::BM, T::BN, 2> sm;
     const GemmItem w = uniform_load(items + blockIdx.x);
     const DistArgs a = uniform_load(jobs + w.job);
-    gemm_tile<WM, WN, BI, BJ, EPI, PREC, VEC>(a, w.tm, w.tn, sm);
+    gemm_tile<WM, WN, BI, BJ, EPI, PREC, VEC, 2>(a, w.tm, w.tn, sm);
 }
 
 // ---- squared norms ----------------------------------------------------------
@@ -607,7 +611,7 @@ __global__ __launch_bounds__(256) void certify_kernel(const float *__restrict__ 
 }
 
 // ---- host launchers ----------------------------------------------------------
-template <int WM, int WN, int BI, int BJ, int EPI>
+template <int WM, int WN, int BI, int BJ, int EPI, int ST = 2>
 static hipError_t launch_gemm_t(const DistArgs &a0, hipStream_t stream) {
     using T = Tile<WM, WN, BI, BJ>;
     DistArgs a = a0;
@@ -618,33 +622,40 @@ static hipError_t launch_gemm_t(const DistArgs &a0, hipStream_t stream) {
     if (grid > 0x7fffffffull) return hipErrorInvalidValue;
     const dim3 g((unsigned)grid), b(T::NT);
     if (a.prec == kPrecBF16) {
-        hipLaunchKernelGGL((dist_gemm_kernel<WM, WN, BI, BJ, EPI, kPrecBF16, true>), g, b, 0, stream, a);
+        hipLaunchKernelGGL((dist_gemm_kernel<WM, WN, BI, BJ, EPI, kPrecBF16, true, ST>), g, b, 0, stream, a);
     } else if (a.prec == kPrecFP8) {
         if constexpr (BI * BJ <= 4)
-            hipLaunchKernelGGL((dist_gemm_kernel<WM, WN, BI, BJ, EPI, kPrecFP8, true>), g, b, 0, stream, a);
+            hipLaunchKernelGGL((dist_gemm_kernel<WM, WN, BI, BJ, EPI, kPrecFP8, true, ST>), g, b, 0, stream, a);
         else
             return hipErrorInvalidValue;
     }
     else if (a.d % 4 == 0)
-        hipLaunchKernelGGL((dist_gemm_kernel<WM, WN, BI, BJ, EPI, kPrecF32, true>), g, b, 0, stream, a);
+        hipLaunchKernelGGL((dist_gemm_kernel<WM, WN, BI, BJ, EPI, kPrecF32, true, ST>), g, b, 0, stream, a);
     else
-        hipLaunchKernelGGL((dist_gemm_kernel<WM, WN, BI, BJ, EPI, kPrecF32, false>), g, b, 0, stream, a);
+        hipLaunchKernelGGL((dist_gemm_kernel<WM, WN, BI, BJ, EPI, kPrecF32, false, ST>), g, b, 0, stream, a);
     return hipGetLastError();
 }
 
 // Tile shapes: small 128 x 128 (4 waves of 64 x 64), wide 128 x 256 (8 waves of
 // 64 x 64), big 256 x 256 (8 waves of 128 x 64; FP32 and BF16 only, its FP8
-// variant exceeds the register file).  Default: big for products that fill the
-// device with such tiles (wide for FP8), small otherwise.  KNN_GEMM_TILE
-// (small / wide / big) overrides the default where the shape is legal.
+// variant exceeds the register file), and small with one operand stage (half
+// the LDS: more workgroups per CU to hide load latency when the K loop is
+// short).  Default for products that fill the device: BF16 / FP8 with
+// d <= 512 small with one stage, otherwise big (wide for FP8); small for the
+// rest.  KNN_GEMM_TILE (small / wide / big / small1) overrides the default
+// where the shape is legal.
 int gemm_tile_choice(const DistArgs &a) {
-    if (a.tile >= kTileSmall && a.tile <= kTileBig) return (a.tile == kTileBig && a.prec == kPrecFP8) ? kTileWide : a.tile;
+    if (a.tile >= kTileSmall && a.tile <= kTileSmall1)
+        return (a.tile == kTileBig && a.prec == kPrecFP8) ? kTileWide : a.tile;
     const bool large = a.m >= 2048 && a.n >= 2048;
-    int t = large ? (a.prec == kPrecFP8 ? kTileWide : kTileBig) : kTileSmall;
+    int t = kTileSmall;
+    if (large && a.prec != kPrecF32 && a.d <= 512) t = kTileSmall1;  // short K loop: latency-bound
+    else if (large) t = a.prec == kPrecFP8 ? kTileWide : kTileBig;
     if (const char *e = std::getenv("KNN_GEMM_TILE")) {
         if (!std::strcmp(e, "small")) t = kTileSmall;
         else if (!std::strcmp(e, "wide")) t = kTileWide;
         else if (!std::strcmp(e, "big") && a.prec != kPrecFP8) t = kTileBig;
+        else if (!std::strcmp(e, "small1")) t = kTileSmall1;
     }
     return t;
 }
@@ -658,6 +669,9 @@ hipError_t launch_dist_gemm(const DistArgs &a, int epi, hipStream_t stream) {
         case kTileWide:
             return epi == kEpiDense ? launch_gemm_t<2, 4, 2, 2, kEpiDense>(a, stream)
                                     : launch_gemm_t<2, 4, 2, 2, kEpiFilter>(a, stream);
+        case kTileSmall1:
+            return epi == kEpiDense ? launch_gemm_t<2, 2, 2, 2, kEpiDense, 1>(a, stream)
+                                    : launch_gemm_t<2, 2, 2, 2, kEpiFilter, 1>(a, stream);
         default:
             return epi == kEpiDense ? launch_gemm_t<2, 2, 2, 2, kEpiDense>(a, stream)
                                     : launch_gemm_t<2, 2, 2, 2, kEpiFilter>(a, stream);

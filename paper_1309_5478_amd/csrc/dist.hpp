@@ -7,7 +7,7 @@ namespace knn {
 
 enum : int { kEpiDense = 0, kEpiFilter = 1 };
 enum : int { kPrecF32 = 0, kPrecBF16 = 1, kPrecFP8 = 2 };
-enum : int { kTileSmall = 0, kTileWide = 1, kTileBig = 2 };
+enum : int { kTileSmall = 0, kTileWide = 1, kTileBig = 2, kTileSmall1 = 3 };
 
 // Quantised operands (BF16 / FP8): rows padded with zeros to a multiple of
 // kQuantPad elements, so every 128-byte k-chunk load is in bounds.

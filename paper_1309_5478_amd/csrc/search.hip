@@ -174,7 +174,7 @@ knn_status_t run_search(knn_handle_t h, const float *Q, int64_t m, const float *
             pa.cand = b.cand;
             pa.cap = p.cap;
             set_prec(pa, qrow(0), qsrow(0), Cq, csc);
-            std::vector<int> cands = {kTileSmall, kTileWide};
+            std::vector<int> cands = {kTileSmall, kTileSmall1, kTileWide};
             if (p.prec != kPrecFP8) cands.push_back(kTileBig);
             auto run = [&](int t) -> hipError_t {
                 pa.tile = t;

@@ -153,3 +153,32 @@ def test_repeat_determinism(h, torch, seed):
     a = run_graph(h, torch, P, 32)
     b = run_graph(h, torch, P, 32)
     assert np.array_equal(a[1], b[1]) and np.array_equal(a[0].view(np.uint32), b[0].view(np.uint32))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+def test_tile_shapes_give_identical_bits(h, torch, prec):
+    """The product's tile shape (and operand stage count) changes no output bit:
+    every element's dot product accumulates in the same order."""
+    import os
+    P = synth.gmm_points(4096, 160, seed=synth.SEEDS["knng_small"] + 50)
+    dev = torch.from_numpy(P).cuda()
+    outs = {}
+    old = os.environ.get("KNN_GEMM_TILE")
+    try:
+        for tile in ("small", "small1", "wide", "big"):
+            if tile == "big" and prec == "fp8":
+                continue
+            os.environ["KNN_GEMM_TILE"] = tile
+            d, i = h.graph(dev, 20, precision=prec)
+            dm = h.distances(dev[:512], dev)
+            torch.cuda.synchronize()
+            outs[tile] = (d.cpu().numpy().view(np.uint32), i.cpu().numpy(), dm.cpu().numpy().view(np.uint32))
+    finally:
+        if old is None:
+            os.environ.pop("KNN_GEMM_TILE", None)
+        else:
+            os.environ["KNN_GEMM_TILE"] = old
+    ref = outs["small"]
+    for tile, o in outs.items():
+        for a, b in zip(o, ref):
+            assert np.array_equal(a, b), (prec, tile)
