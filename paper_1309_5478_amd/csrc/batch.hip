@@ -47,24 +47,6 @@ hipError_t launch_sum_u32(const uint32_t *p, int64_t n, unsigned long long *out,
 knn_status_t run_search(knn_handle_t h, const float *Q, int64_t m, const float *C, int64_t n, int d, int k, bool graph,
                         float *out_dist, int32_t *out_idx, hipStream_t stream, const knn_options_t *opt);
 
-namespace {
-
-// dst[i] = src[i * stride], i < rows: the threshold column of a sample selection.
-__global__ __launch_bounds__(256) void column_copy_kernel(const float *__restrict__ src, int64_t stride, int64_t rows,
-                                                          float *__restrict__ dst) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < rows) dst[i] = src[i * stride];
-}
-
-hipError_t launch_column_copy(const float *src, int64_t stride, int64_t rows, float *dst, hipStream_t s) {
-    if (rows == 0) return hipSuccess;
-    hipLaunchKernelGGL(column_copy_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, src, stride, rows,
-                       dst);
-    return hipGetLastError();
-}
-
-}  // namespace
-
 struct BatchJob {
     const float *Q, *C;
     int64_t m, n;
@@ -79,31 +61,50 @@ struct BatchJob {
     unsigned int *cmax2 = nullptr;
     void *Cq = nullptr, *Qq = nullptr;
     float *cs = nullptr, *qs = nullptr;
+    // the threshold sample of the corpus (the corpus itself when not gathered)
+    const float *Cs = nullptr, *csn = nullptr, *css = nullptr;
+    const void *Csq = nullptr;
     int first_part = 0, nparts = 0;
 };
 
 struct BatchPart {
     int job;
     int64_t i0, mb;
-    bool direct;   // the threshold sample is the whole corpus: its selection is the candidate list
-    bool grouped;  // in the grouped launch (else its own launch: FP32 with d % 4 != 0)
-    float *tau = nullptr;
+    bool direct;    // the threshold sample is the whole corpus: its selection is the candidate list
+    bool grouped;   // FILTER product in the grouped launch (else its own: FP32 with d % 4 != 0)
+    bool sgrouped;  // sample product in the grouped launch (same condition)
+    float *Ds = nullptr;   // mb x S sample distances
+    float *tv = nullptr;   // mb x (r + 1) selected sample keys (values, indices)
+    int32_t *ti = nullptr;
     uint32_t *cnt = nullptr;
     uint64_t *cand = nullptr;
     int32_t *flags = nullptr;
+    float *sv = nullptr;   // mb x kk selected candidates
+    int32_t *si = nullptr;
+};
+
+// A multi-matrix selection launch: its segments and the segment of each row.
+struct SegLaunch {
+    int cap = 0;
+    int64_t rows = 0;
+    uint32_t cols = 0, k = 0;
+    std::vector<SelectSeg> segs;
+    std::vector<uint32_t> row_seg;
+    SelectSeg *dsegs = nullptr;
+    uint32_t *drow_seg = nullptr;
 };
 
 // Buffers shared by all jobs; every use of one is ordered on the stream.
 struct BatchShared {
-    float *Cs = nullptr, *csn = nullptr, *css = nullptr, *Ds = nullptr, *tv = nullptr;
-    void *Csq = nullptr, *Qfq = nullptr;
-    int32_t *ti = nullptr;
-    float *sv = nullptr, *Qf = nullptr, *Df = nullptr, *fv = nullptr, *qfs = nullptr;
-    int32_t *si = nullptr, *fi = nullptr;
+    float *Qf = nullptr, *Df = nullptr, *fv = nullptr, *qfs = nullptr;
+    void *Qfq = nullptr;
+    int32_t *fi = nullptr;
     void *selws = nullptr;
     float *ninf = nullptr;
-    DistArgs *table = nullptr, *probe = nullptr;
-    GemmItem *items = nullptr;
+    uint32_t *cnt_all = nullptr;  // the candidate counts of all parts, contiguous
+    int64_t cnt_rows = 0;
+    DistArgs *table = nullptr, *probe = nullptr, *stable = nullptr;
+    GemmItem *items = nullptr, *sitems = nullptr;
     uint32_t *nflag = nullptr;
 };
 
@@ -123,7 +124,9 @@ struct BatchState {
     std::vector<int> order;  // jobs, longest first
     BatchShared sh;
     int tile = kTileWide;
-    size_t nitems = 0;
+    size_t nitems = 0, nsitems = 0;
+    std::vector<SegLaunch> sample_sel;  // threshold selections, one launch per capacity class
+    SegLaunch keys_sel;                 // candidate selections
     int smode = kPivotSample;
     const uint16_t *net = nullptr;
     int force = 0;
@@ -201,10 +204,74 @@ size_t max_items(const BatchState &b) {
     return n;
 }
 
-// Lays out the batch workspace (sizing pass with base == nullptr).
+// Items of the grouped sample products (128 x 128 tiles), part after part.
+void build_sample_items(const BatchState &b, std::vector<GemmItem> &items) {
+    items.clear();
+    for (size_t pi = 0; pi < b.parts.size(); ++pi) {
+        const BatchPart &pt = b.parts[pi];
+        if (!pt.sgrouped) continue;
+        const uint32_t tm_n = (uint32_t)((pt.mb + 127) / 128), tn_n = (uint32_t)((b.jobs[pt.job].p.S + 127) / 128);
+        for (uint32_t tm = 0; tm < tm_n; ++tm)
+            for (uint32_t tn = 0; tn < tn_n; ++tn) items.push_back(GemmItem{(uint32_t)pi, tm, tn});
+    }
+}
+
+// The threshold selections of all parts (k = r + 1 over their S sample
+// distances), one launch per capacity class, and the candidate selections of
+// the filtered parts (k = kk over their candidate lists), one launch.
+void plan_selects(BatchState &b) {
+    b.sample_sel.clear();
+    for (int cap : {1024, 2048, 4096}) {
+        SegLaunch L;
+        L.cap = cap;
+        for (const BatchPart &pt : b.parts) {
+            const Plan &p = b.jobs[pt.job].p;
+            if (select_cap_for_k((uint32_t)(p.r + 1)) != cap) continue;
+            SelectSeg sg{};
+            sg.dist = pt.Ds;
+            sg.ld = p.S;
+            sg.row0 = L.rows;
+            sg.cols = (uint32_t)p.S;
+            sg.k = (uint32_t)(p.r + 1);
+            sg.out_val = pt.tv;
+            sg.out_idx = pt.ti;
+            L.cols = std::max(L.cols, sg.cols);
+            L.k = std::max(L.k, sg.k);
+            for (int64_t i = 0; i < pt.mb; ++i) L.row_seg.push_back((uint32_t)L.segs.size());
+            L.segs.push_back(sg);
+            L.rows += pt.mb;
+        }
+        if (L.rows) b.sample_sel.push_back(std::move(L));
+    }
+    SegLaunch K;
+    K.cap = kSelectKeysCap;
+    for (const BatchPart &pt : b.parts) {
+        if (pt.direct) continue;
+        const Plan &p = b.jobs[pt.job].p;
+        SelectSeg sg{};
+        sg.keys = pt.cand;
+        sg.key_cnt = pt.cnt;
+        sg.ld = p.cap;
+        sg.row0 = K.rows;
+        sg.cols = (uint32_t)p.cap;
+        sg.k = (uint32_t)p.kk;
+        sg.out_val = pt.sv;
+        sg.out_idx = pt.si;
+        K.cols = std::max(K.cols, sg.cols);
+        K.k = std::max(K.k, sg.k);
+        for (int64_t i = 0; i < pt.mb; ++i) K.row_seg.push_back((uint32_t)K.segs.size());
+        K.segs.push_back(sg);
+        K.rows += pt.mb;
+    }
+    b.keys_sel = std::move(K);
+}
+
+// Lays out the batch workspace (sizing pass with base == nullptr).  Every
+// part keeps its own sample distances, selections and candidate lists, so
+// each phase can run as one launch over all parts.
 size_t carve_batch(Carve &c, BatchState &b, int num_cu, bool probe) {
     BatchShared &s = b.sh;
-    size_t cs = 0, csq = 0, ds = 0, tv = 0, sv = 0, qf = 0, df = 0, fv = 0, qfq = 0, fb = 0, selws = 0, S = 0;
+    size_t qf = 0, df = 0, fv = 0, qfq = 0, fb = 0, selws = 0;
     for (BatchJob &js : b.jobs) {
         const Plan &p = js.p;
         js.cnorm = c.take<float>(js.n);
@@ -221,41 +288,53 @@ size_t carve_batch(Carve &c, BatchState &b, int num_cu, bool probe) {
                 js.qs = js.cs;
             }
         }
-        if (p.gathered) {
-            cs = std::max(cs, (size_t)p.S * p.d);
-            csq = std::max(csq, (size_t)p.S * p.ldq);
+        js.Cs = js.C;
+        js.csn = js.cnorm;
+        js.Csq = js.Cq;
+        js.css = js.cs;
+        if (p.gathered && js.nparts) {
+            js.Cs = c.take<float>((size_t)p.S * p.d);
+            js.csn = c.take<float>(p.S);
+            if (p.prec != kPrecF32) {
+                js.Csq = c.take<char>((size_t)p.S * p.ldq);
+                js.css = c.take<float>(p.S);
+            }
         }
-        S = std::max(S, (size_t)p.S);
-        ds = std::max(ds, (size_t)p.Mb * p.S);
-        tv = std::max(tv, (size_t)p.Mb * (p.r + 1));
-        sv = std::max(sv, (size_t)p.Mb * p.kk);
         qf = std::max(qf, (size_t)p.Fb * p.d);
         df = std::max(df, (size_t)p.Fb * js.n);
         fv = std::max(fv, (size_t)p.Fb * p.kk);
         qfq = std::max(qfq, (size_t)p.Fb * p.ldq);
         fb = std::max(fb, (size_t)p.Fb);
-        const int cap1 = select_cap_for_k(p.r + 1);
         const int cap2 = select_cap_for_k(p.kk);
-        selws = std::max(selws, select_ws_bytes(cap1, (uint32_t)p.S, select_grid(cap1, p.Mb, num_cu)));
         selws = std::max(selws, select_ws_bytes(cap2, (uint32_t)js.n, select_grid(cap2, p.Fb, num_cu)));
     }
+    int64_t cnt_rows = 0;
+    for (const BatchPart &pt : b.parts)
+        if (!pt.direct) cnt_rows += pt.mb;
+    s.cnt_all = c.take<uint32_t>((size_t)std::max<int64_t>(cnt_rows, 1));
+    s.cnt_rows = cnt_rows;
+    int64_t cnt_off = 0;
     for (BatchPart &pt : b.parts) {
         const Plan &p = b.jobs[pt.job].p;
+        pt.Ds = c.take<float>((size_t)pt.mb * p.S);
+        pt.tv = c.take<float>((size_t)pt.mb * (p.r + 1));
+        pt.ti = c.take<int32_t>((size_t)pt.mb * (p.r + 1));
         if (pt.direct) continue;
-        pt.tau = c.take<float>(pt.mb);
-        pt.cnt = c.take<uint32_t>(pt.mb);
+        pt.cnt = s.cnt_all ? s.cnt_all + cnt_off : nullptr;
+        cnt_off += pt.mb;
         pt.cand = c.take<uint64_t>((size_t)pt.mb * p.cap);
         pt.flags = c.take<int32_t>(pt.mb);
+        pt.sv = c.take<float>((size_t)pt.mb * p.kk);
+        pt.si = c.take<int32_t>((size_t)pt.mb * p.kk);
     }
-    s.Cs = c.take<float>(cs);
-    s.csn = c.take<float>(S);
-    s.Csq = c.take<char>(csq);
-    s.css = c.take<float>(S);
-    s.Ds = c.take<float>(ds);
-    s.tv = c.take<float>(tv);
-    s.ti = c.take<int32_t>(tv);
-    s.sv = c.take<float>(sv);
-    s.si = c.take<int32_t>(sv);
+    plan_selects(b);
+    for (SegLaunch &L : b.sample_sel) {
+        selws = std::max(selws, select_ws_bytes(L.cap, L.cols, select_grid(L.cap, L.rows, num_cu)));
+        L.dsegs = c.take<SelectSeg>(L.segs.size());
+        L.drow_seg = c.take<uint32_t>((size_t)L.rows);
+    }
+    b.keys_sel.dsegs = c.take<SelectSeg>(std::max<size_t>(b.keys_sel.segs.size(), 1));
+    b.keys_sel.drow_seg = c.take<uint32_t>((size_t)std::max<int64_t>(b.keys_sel.rows, 1));
     s.Qf = c.take<float>(qf);
     s.Df = c.take<float>(df);
     s.fv = c.take<float>(fv);
@@ -265,8 +344,13 @@ size_t carve_batch(Carve &c, BatchState &b, int num_cu, bool probe) {
     s.selws = c.take<char>(selws < 256 ? 256 : selws);
     s.ninf = c.take<float>(1);
     s.table = c.take<DistArgs>(b.parts.size());
+    s.stable = c.take<DistArgs>(b.parts.size());
     s.probe = probe ? c.take<DistArgs>(b.parts.size()) : nullptr;
     s.items = c.take<GemmItem>(std::max<size_t>(max_items(b), 1));
+    std::vector<GemmItem> si;
+    build_sample_items(b, si);
+    s.sitems = c.take<GemmItem>(std::max<size_t>(si.size(), 1));
+    b.nsitems = si.size();
     s.nflag = c.take<uint32_t>(b.parts.size());
     return c.off;
 }
@@ -282,8 +366,8 @@ DistArgs part_args(const BatchState &b, const BatchPart &pt) {
     a.d = js.d;
     a.cnorm = js.cnorm;
     a.self_offset = js.graph ? pt.i0 : -1;
-    a.tau = pt.tau;
-    a.tau_stride = 1;
+    a.tau = pt.tv ? pt.tv + p.r : nullptr;  // the threshold is the last selected sample key
+    a.tau_stride = p.r + 1;
     a.cnt = pt.cnt;
     a.cand = pt.cand;
     a.cap = p.cap;
@@ -296,6 +380,37 @@ DistArgs part_args(const BatchState &b, const BatchPart &pt) {
     return a;
 }
 
+// The sample product of a part: its rows against the job's threshold sample.
+DistArgs sample_args(const BatchState &b, const BatchPart &pt) {
+    const BatchJob &js = b.jobs[pt.job];
+    const Plan &p = js.p;
+    DistArgs sa = part_args(b, pt);
+    sa.C = js.Cs;
+    sa.n = p.S;
+    sa.cnorm = js.csn;
+    sa.self_offset = (js.graph && !p.gathered) ? pt.i0 : -1;
+    sa.out = pt.Ds;
+    sa.ldo = p.S;
+    sa.tau = nullptr;
+    sa.cnt = nullptr;
+    sa.cand = nullptr;
+    sa.Cq = js.Csq;
+    sa.cscale = js.css;
+    return sa;
+}
+
+SelectArgs seg_select_args(const BatchState &b, const SegLaunch &L) {
+    SelectArgs a{};
+    a.rows = L.rows;
+    a.cols = L.cols;
+    a.k = L.k;
+    a.mode = b.smode;
+    a.net = b.smode == kPivotLearned ? b.net : nullptr;
+    a.segs = L.dsegs;
+    a.row_seg = L.drow_seg;
+    return a;
+}
+
 // ---- the phases, enqueued on a stream (captured or eager) ------------------
 hipError_t enqueue_prep(const BatchState &b, knn_handle_t h, int num_cu, hipStream_t s) {
     hipError_t e = hipSuccess;
@@ -304,6 +419,7 @@ hipError_t enqueue_prep(const BatchState &b, knn_handle_t h, int num_cu, hipStre
     do {                                           \
         if ((e = (call)) != hipSuccess) return e;  \
     } while (0)
+    // per job: norms, quantised copies, the gathered threshold sample
     for (int j : b.order) {
         const BatchJob &js = b.jobs[j];
         const Plan &p = js.p;
@@ -315,47 +431,37 @@ hipError_t enqueue_prep(const BatchState &b, knn_handle_t h, int num_cu, hipStre
             BTRY(launch_quantize(js.C, js.n, js.d, p.prec, js.Cq, js.cs, s));
             if (!js.graph) BTRY(launch_quantize(js.Q, js.m, js.d, p.prec, js.Qq, js.qs, s));
         }
-        const float *Cs = js.C, *csn = js.cnorm, *css = js.cs;
-        const void *Csq = js.Cq;
         if (p.gathered) {
-            BTRY(launch_gather_rows(js.C, js.n, js.d, nullptr, p.S, sh.Cs, js.cnorm, sh.csn, s));
-            Cs = sh.Cs;
-            csn = sh.csn;
-            if (p.prec != kPrecF32) {
-                BTRY(launch_quantize(sh.Cs, p.S, js.d, p.prec, sh.Csq, sh.css, s));
-                Csq = sh.Csq;
-                css = sh.css;
-            }
-        }
-        for (int pi = js.first_part; pi < js.first_part + js.nparts; ++pi) {
-            const BatchPart &pt = b.parts[pi];
-            DistArgs sa = part_args(b, pt);
-            sa.C = Cs;
-            sa.n = p.S;
-            sa.cnorm = csn;
-            sa.self_offset = (js.graph && !p.gathered) ? pt.i0 : -1;
-            sa.out = sh.Ds;
-            sa.ldo = p.S;
-            sa.tau = nullptr;
-            sa.cnt = nullptr;
-            sa.cand = nullptr;
-            sa.Cq = Csq;
-            sa.cscale = css;
-            BTRY(launch_dist_gemm(sa, kEpiDense, s));
-            BTRY(select_dense(sh.Ds, pt.mb, p.S, p.S, p.r + 1, sh.tv, sh.ti, sh.selws, num_cu, b.smode, b.net, s));
-            if (pt.direct) {  // the row's kk smallest keys, in order: certify and re-rank now
-                if (p.kk < p.n_eff)
-                    BTRY(launch_certify(sh.tv, pt.mb, p.kk, js.k, js.qn2 + pt.i0, js.cmax2, p.rel,
-                                        stats_ptr(h) + kStatUncertified, s));
-                RerankArgs rr{js.Q + pt.i0 * js.d, pt.mb, js.C, js.n, js.d, sh.ti, (uint32_t)p.kk, js.k,
-                              js.out_dist + pt.i0 * js.k, js.out_idx + pt.i0 * js.k};
-                BTRY(launch_rerank(rr, s));
-                continue;
-            }
-            BTRY(launch_column_copy(sh.tv + p.r, p.r + 1, pt.mb, pt.tau, s));
-            BTRY(launch_fill_u32(pt.cnt, pt.mb, 0u, s));
+            float *Cs = const_cast<float *>(js.Cs), *csn = const_cast<float *>(js.csn);
+            BTRY(launch_gather_rows(js.C, js.n, js.d, nullptr, p.S, Cs, js.cnorm, csn, s));
+            if (p.prec != kPrecF32)
+                BTRY(launch_quantize(Cs, p.S, js.d, p.prec, const_cast<void *>(js.Csq), const_cast<float *>(js.css),
+                                     s));
         }
     }
+    // all sample products in one launch (FP32 parts with d % 4 != 0 on their own)
+    BTRY(launch_dist_gemm_grouped(sh.stable, sh.sitems, (int64_t)b.nsitems, b.jobs[0].p.prec, kTileSmall, s,
+                                  kEpiDense));
+    for (const BatchPart &pt : b.parts)
+        if (!pt.sgrouped) BTRY(launch_dist_gemm(sample_args(b, pt), kEpiDense, s));
+    // all threshold selections, one launch per capacity class
+    for (const SegLaunch &L : b.sample_sel) {
+        SelectArgs sa = seg_select_args(b, L);
+        BTRY(launch_select(sa, L.cap, select_grid(L.cap, L.rows, num_cu), sh.selws, s));
+    }
+    // parts whose sample is the whole corpus: certificate and re-rank now
+    for (const BatchPart &pt : b.parts) {
+        if (!pt.direct) continue;
+        const BatchJob &js = b.jobs[pt.job];
+        const Plan &p = js.p;
+        if (p.kk < p.n_eff)
+            BTRY(launch_certify(pt.tv, pt.mb, p.kk, js.k, js.qn2 + pt.i0, js.cmax2, p.rel,
+                                stats_ptr(h) + kStatUncertified, s));
+        RerankArgs rr{js.Q + pt.i0 * js.d, pt.mb, js.C, js.n, js.d, pt.ti, (uint32_t)p.kk, js.k,
+                      js.out_dist + pt.i0 * js.k, js.out_idx + pt.i0 * js.k};
+        BTRY(launch_rerank(rr, s));
+    }
+    if (sh.cnt_rows) BTRY(launch_fill_u32(sh.cnt_all, sh.cnt_rows, 0u, s));
     return e;
 }
 
@@ -377,11 +483,11 @@ hipError_t enqueue_product(const BatchState &b, const DistArgs *table, int tile,
 hipError_t enqueue_flags(const BatchState &b, knn_handle_t h, hipStream_t s) {
     hipError_t e = hipSuccess;
     BTRY(launch_fill_u32(b.sh.nflag, (int64_t)b.parts.size(), 0u, s));
+    if (b.sh.cnt_rows) BTRY(launch_sum_u32(b.sh.cnt_all, b.sh.cnt_rows, stats_ptr(h) + kStatCandidates, s));
     for (size_t pi = 0; pi < b.parts.size(); ++pi) {
         const BatchPart &pt = b.parts[pi];
         const Plan &p = b.jobs[pt.job].p;
         if (pt.direct) continue;
-        BTRY(launch_sum_u32(pt.cnt, pt.mb, stats_ptr(h) + kStatCandidates, s));
         BTRY(launch_flag_rows(pt.cnt, pt.mb, (uint32_t)p.kk, (uint32_t)p.cap, b.force, b.sh.nflag + pi, pt.flags, s));
     }
     return hipMemcpyAsync(b.nflag_host, b.sh.nflag, b.parts.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
@@ -389,32 +495,21 @@ hipError_t enqueue_flags(const BatchState &b, knn_handle_t h, hipStream_t s) {
 
 hipError_t enqueue_final(const BatchState &b, knn_handle_t h, int num_cu, hipStream_t s) {
     hipError_t e = hipSuccess;
-    const BatchShared &sh = b.sh;
-    for (int j : b.order) {
-        const BatchJob &js = b.jobs[j];
+    // the kk smallest candidate keys of every filtered row, one launch
+    if (b.keys_sel.rows) {
+        SelectArgs ka = seg_select_args(b, b.keys_sel);
+        BTRY(launch_select_keys(ka, ka.rows, num_cu, s));
+    }
+    for (const BatchPart &pt : b.parts) {
+        if (pt.direct) continue;
+        const BatchJob &js = b.jobs[pt.job];
         const Plan &p = js.p;
-        for (int pi = js.first_part; pi < js.first_part + js.nparts; ++pi) {
-            const BatchPart &pt = b.parts[pi];
-            if (pt.direct) continue;
-            SelectArgs ka{};
-            ka.keys = pt.cand;
-            ka.key_cnt = pt.cnt;
-            ka.rows = pt.mb;
-            ka.cols = (uint32_t)p.cap;
-            ka.ld = p.cap;
-            ka.k = (uint32_t)p.kk;
-            ka.out_val = sh.sv;
-            ka.out_idx = sh.si;
-            ka.mode = b.smode;
-            ka.net = b.smode == kPivotLearned ? b.net : nullptr;
-            BTRY(launch_select_keys(ka, pt.mb, num_cu, s));
-            if (p.kk < p.n_eff)
-                BTRY(launch_certify(sh.sv, pt.mb, p.kk, js.k, js.qn2 + pt.i0, js.cmax2, p.rel,
-                                    stats_ptr(h) + kStatUncertified, s));
-            RerankArgs rr{js.Q + pt.i0 * js.d, pt.mb, js.C, js.n, js.d, sh.si, (uint32_t)p.kk, js.k,
-                          js.out_dist + pt.i0 * js.k, js.out_idx + pt.i0 * js.k};
-            BTRY(launch_rerank(rr, s));
-        }
+        if (p.kk < p.n_eff)
+            BTRY(launch_certify(pt.sv, pt.mb, p.kk, js.k, js.qn2 + pt.i0, js.cmax2, p.rel,
+                                stats_ptr(h) + kStatUncertified, s));
+        RerankArgs rr{js.Q + pt.i0 * js.d, pt.mb, js.C, js.n, js.d, pt.si, (uint32_t)p.kk, js.k,
+                      js.out_dist + pt.i0 * js.k, js.out_idx + pt.i0 * js.k};
+        BTRY(launch_rerank(rr, s));
     }
     return e;
 }
@@ -565,7 +660,8 @@ knn_status_t run_batch(knn_handle_t h, const knn_job_t *jobs, int32_t njobs, hip
                 pt.i0 = i0;
                 pt.mb = jb.m - i0 < js.p.Mb ? jb.m - i0 : js.p.Mb;
                 pt.direct = !js.p.gathered;
-                pt.grouped = !pt.direct && !(js.p.prec == kPrecF32 && js.d % 4 != 0);
+                pt.sgrouped = !(js.p.prec == kPrecF32 && js.d % 4 != 0);
+                pt.grouped = !pt.direct && pt.sgrouped;
                 b.parts.push_back(pt);
             }
             js.nparts = (int)b.parts.size() - js.first_part;
@@ -613,6 +709,26 @@ knn_status_t run_batch(knn_handle_t h, const knn_job_t *jobs, int32_t njobs, hip
         std::vector<DistArgs> table(b.parts.size());
         for (size_t pi = 0; pi < b.parts.size(); ++pi) table[pi] = part_args(b, b.parts[pi]);
         KTRY(hipMemcpyAsync(b.sh.table, table.data(), table.size() * sizeof(DistArgs), hipMemcpyHostToDevice, stream));
+        std::vector<DistArgs> stable(b.parts.size());
+        for (size_t pi = 0; pi < b.parts.size(); ++pi) stable[pi] = sample_args(b, b.parts[pi]);
+        KTRY(hipMemcpyAsync(b.sh.stable, stable.data(), stable.size() * sizeof(DistArgs), hipMemcpyHostToDevice,
+                            stream));
+        std::vector<GemmItem> sitems;
+        build_sample_items(b, sitems);
+        if (!sitems.empty())
+            KTRY(hipMemcpyAsync(b.sh.sitems, sitems.data(), sitems.size() * sizeof(GemmItem), hipMemcpyHostToDevice,
+                                stream));
+        std::vector<SegLaunch *> launches;
+        for (SegLaunch &L : b.sample_sel) launches.push_back(&L);
+        launches.push_back(&b.keys_sel);
+        for (SegLaunch *L : launches) {
+            if (!L->rows) continue;
+            KTRY(hipMemcpyAsync(L->dsegs, L->segs.data(), L->segs.size() * sizeof(SelectSeg), hipMemcpyHostToDevice,
+                                stream));
+            KTRY(hipMemcpyAsync(L->drow_seg, L->row_seg.data(), L->row_seg.size() * sizeof(uint32_t),
+                                hipMemcpyHostToDevice, stream));
+        }
+        KTRY(hipStreamSynchronize(stream));  // the host vectors above are released at scope end
         KTRY(launch_fill_u32(reinterpret_cast<uint32_t *>(b.sh.ninf), 1, 0xFF800000u, stream));
         const int prec = b.jobs[0].p.prec;
         b.tile = prec == kPrecFP8 ? kTileWide : kTileBig;

@@ -328,19 +328,6 @@ __global__ __launch_bounds__(64 * WM * WN) void dist_gemm_kernel(DistArgs a) {
     gemm_tile<WM, WN, BI, BJ, EPI, PREC, VEC, ST>(a, tm, tn, sm);
 }
 
-// A structure at an address that is the same in every lane, held in scalar
-// registers (vector loads of the same words, then the first lane's copy).
-template <class T>
-__device__ __forceinline__ T uniform_load(const T *p) {
-    static_assert(sizeof(T) % 4 == 0, "whole dwords");
-    T v;
-    const uint32_t *src = reinterpret_cast<const uint32_t *>(p);
-    uint32_t *dst = reinterpret_cast<uint32_t *>(&v);
-#pragma unroll
-    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
-    return v;
-}
-
 // Grouped product: workgroup b computes item b of a list of (job, row tile,
 // column tile) items that the host has put in dispatch order (workgroup b runs
 // on XCD b % 8).  One item per workgroup, as in the single product: a
@@ -686,38 +673,42 @@ void gemm_tile_dims(int tile, int *bm, int *bn) {
     }
 }
 
-template <int WM, int WN, int BI, int BJ>
+template <int WM, int WN, int BI, int BJ, int EPI>
 static hipError_t launch_grouped_t(const DistArgs *jobs, const GemmItem *items, int64_t grid, int prec,
                                    hipStream_t stream) {
     const dim3 g((unsigned)grid), b(Tile<WM, WN, BI, BJ>::NT);
     if (prec == kPrecBF16)
-        hipLaunchKernelGGL((dist_gemm_grouped_kernel<WM, WN, BI, BJ, kEpiFilter, kPrecBF16, true>), g, b, 0, stream,
-                           jobs, items);
+        hipLaunchKernelGGL((dist_gemm_grouped_kernel<WM, WN, BI, BJ, EPI, kPrecBF16, true>), g, b, 0, stream, jobs,
+                           items);
     else if (prec == kPrecFP8) {
         if constexpr (BI * BJ <= 4)
-            hipLaunchKernelGGL((dist_gemm_grouped_kernel<WM, WN, BI, BJ, kEpiFilter, kPrecFP8, true>), g, b, 0, stream,
-                               jobs, items);
+            hipLaunchKernelGGL((dist_gemm_grouped_kernel<WM, WN, BI, BJ, EPI, kPrecFP8, true>), g, b, 0, stream, jobs,
+                               items);
         else
             return hipErrorInvalidValue;
     } else
-        hipLaunchKernelGGL((dist_gemm_grouped_kernel<WM, WN, BI, BJ, kEpiFilter, kPrecF32, true>), g, b, 0, stream,
-                           jobs, items);
+        hipLaunchKernelGGL((dist_gemm_grouped_kernel<WM, WN, BI, BJ, EPI, kPrecF32, true>), g, b, 0, stream, jobs,
+                           items);
     return hipGetLastError();
 }
 
 hipError_t launch_dist_gemm_grouped(const DistArgs *jobs, const GemmItem *items, int64_t nitems, int prec, int tile,
-                                    hipStream_t stream) {
+                                    hipStream_t stream, int epi) {
     if (nitems == 0) return hipSuccess;
     if (nitems > 0x7fffffff) return hipErrorInvalidValue;
     const int64_t grid = nitems;
+    if (epi == kEpiDense) {
+        if (tile != kTileSmall) return hipErrorInvalidValue;
+        return launch_grouped_t<2, 2, 2, 2, kEpiDense>(jobs, items, grid, prec, stream);
+    }
     switch (tile) {
         case kTileBig:
             if (prec == kPrecFP8) return hipErrorInvalidValue;  // FP8 has no 256 x 256 instance
             if (prec == kPrecBF16)
-                return launch_grouped_t<2, 4, 4, 2>(jobs, items, grid, kPrecBF16, stream);
-            return launch_grouped_t<2, 4, 4, 2>(jobs, items, grid, kPrecF32, stream);
-        case kTileWide: return launch_grouped_t<2, 4, 2, 2>(jobs, items, grid, prec, stream);
-        default: return launch_grouped_t<2, 2, 2, 2>(jobs, items, grid, prec, stream);
+                return launch_grouped_t<2, 4, 4, 2, kEpiFilter>(jobs, items, grid, kPrecBF16, stream);
+            return launch_grouped_t<2, 4, 4, 2, kEpiFilter>(jobs, items, grid, kPrecF32, stream);
+        case kTileWide: return launch_grouped_t<2, 4, 2, 2, kEpiFilter>(jobs, items, grid, prec, stream);
+        default: return launch_grouped_t<2, 2, 2, 2, kEpiFilter>(jobs, items, grid, prec, stream);
     }
 }
 

@@ -73,9 +73,9 @@ void gemm_tile_dims(int tile, int *bm, int *bn);
 // One workgroup per item: jobs is a device array of DistArgs (tiles_m /
 // tiles_n / tile unused), items a device array of nitems tiles of the shape
 // `tile`, in dispatch order (item b runs on XCD b % 8).  FP32 jobs need
-// d % 4 == 0.  FILTER epilogue only.
+// d % 4 == 0.  The DENSE epilogue only with the small tile.
 hipError_t launch_dist_gemm_grouped(const DistArgs *jobs, const GemmItem *items, int64_t nitems, int prec, int tile,
-                                    hipStream_t stream);
+                                    hipStream_t stream, int epi = kEpiFilter);
 // Tile shape launch_dist_gemm uses for `a` (kTile*).
 int gemm_tile_choice(const DistArgs &a);
 // Squared norms of n rows of d floats into out; with max_bits (non-null, zero or

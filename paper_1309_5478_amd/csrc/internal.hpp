@@ -27,6 +27,20 @@ enum StatSlot : int {
 };
 
 // ---- selection over a given FP32 matrix ------------------------------------
+// One matrix of a multi-matrix selection: its rows are rows row0 .. of the
+// launch.  Either dense rows (dist, row stride ld) or key-list rows (keys,
+// key_cnt, row stride ld), as in SelectArgs.
+struct SelectSeg {
+    const float *dist;
+    const uint64_t *keys;
+    const uint32_t *key_cnt;
+    int64_t ld;
+    int64_t row0;
+    uint32_t cols, k;
+    float *out_val;        // rows x k
+    int32_t *out_idx;      // rows x k
+};
+
 struct SelectArgs {
     const float *dist;     // rows x cols, row stride ld
     int64_t rows;
@@ -42,6 +56,12 @@ struct SelectArgs {
     const uint32_t *key_cnt;
     int mode;              // PivotMode
     unsigned long long *stats;  // kStatCount counters, or null
+    // several matrices in one launch: row r belongs to segs[row_seg[r]]; then
+    // rows is the total, cols and k the largest of the segments (they size the
+    // workspace and the capacity class), and dist / keys / outputs come from
+    // the segments
+    const SelectSeg *segs;
+    const uint32_t *row_seg;
 };
 
 // Largest k a selection call supports.

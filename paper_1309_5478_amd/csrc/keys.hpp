@@ -80,6 +80,19 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int mask) {
     return ((uint64_t)hi << 32) | lo;
 }
 
+// A structure at an address that is the same in every lane, held in scalar
+// registers (vector loads of the same words, then the first lane's copy).
+template <class T>
+__device__ __forceinline__ T uniform_load(const T *p) {
+    static_assert(sizeof(T) % 4 == 0, "whole dwords");
+    T v;
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(p);
+    uint32_t *dst = reinterpret_cast<uint32_t *>(&v);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
+    return v;
+}
+
 // Ascending bitonic sort of one key per lane across the 64 lanes of a wave.
 __device__ __forceinline__ uint64_t wave_sort64(uint64_t key) {
     const uint32_t lane = lane_id();

@@ -347,24 +347,43 @@ __global__ __launch_bounds__(kSelThreads, (CAP == 1024 && !KEYS) ? 4 : 1) void s
     __shared__ SelSmem<CAP> sm;
     static_assert(sizeof(sm.buf) >= (size_t)(kNetParams + 1) * 2, "partition buffers must hold the pivot network");
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
-    const uint32_t N = a.cols, k = a.k;
     GBuf gb{ws + (uint64_t)blockIdx.x * 2 * ws_slot, ws + (uint64_t)blockIdx.x * 2 * ws_slot + ws_slot};
-    const bool vec = ((reinterpret_cast<uintptr_t>(a.dist) & 15u) == 0) && ((a.ld & 3) == 0);
 
     // per-workgroup totals of the row statistics, in LDS (kept by thread 0)
     if (tid < kAccSlots) sm.acc[tid] = 0;
     __syncthreads();
     for (int64_t r = blockIdx.x; r < a.rows; r += gridDim.x) {
-        const float *row = a.dist + r * a.ld;
+        // this row's matrix: the launch's own, or one segment of several
+        const float *dist = a.dist;
+        const uint64_t *keys = a.keys;
+        const uint32_t *key_cnt = a.key_cnt;
+        int64_t ld = a.ld, lr = r;
+        uint32_t N = a.cols, k = a.k;
+        float *out_val = a.out_val;
+        int32_t *out_idx = a.out_idx;
+        if (a.segs) {
+            const SelectSeg sg = uniform_load(a.segs + __builtin_amdgcn_readfirstlane(a.row_seg[r]));
+            dist = sg.dist;
+            keys = sg.keys;
+            key_cnt = sg.key_cnt;
+            ld = sg.ld;
+            lr = r - sg.row0;
+            N = sg.cols;
+            k = sg.k;
+            out_val = sg.out_val;
+            out_idx = sg.out_idx;
+        }
+        const float *row = dist + lr * ld;
+        const bool vec = ((reinterpret_cast<uintptr_t>(dist) & 15u) == 0) && ((ld & 3) == 0);
         uint32_t nstack = 0, agg = 0, passes = 0, stream_passes = 0, spill = 0, first = 0;
         long long cyc_sample = 0, cyc_stream = 0;
         uint32_t sb, ss, se, Kp;  // active segment (buffer, start, end) and keys still needed
 
         if (KEYS) {
             // key-list row (at most CAP keys, at least k of them)
-            const uint32_t c = a.key_cnt[r];
+            const uint32_t c = key_cnt[lr];
             const uint32_t n = c < N ? c : N;
-            const uint64_t *src = a.keys + r * a.ld;
+            const uint64_t *src = keys + lr * ld;
             for (uint32_t p = tid; p < n; p += kSelThreads) sm.buf[0][p] = src[p];
             __syncthreads();
             sb = 0; ss = 0; se = n; Kp = k;
@@ -560,8 +579,8 @@ __global__ __launch_bounds__(kSelThreads, (CAP == 1024 && !KEYS) ? 4 : 1) void s
             } else {
                 v = (!KEYS && (o == kOrdZero || o == kOrdNaN)) ? row[idx] : ord_to_float(o);
             }
-            a.out_val[r * k + t] = v;
-            a.out_idx[r * k + t] = (int32_t)idx;
+            out_val[lr * k + t] = v;
+            out_idx[lr * k + t] = (int32_t)idx;
         };
         if (k <= (uint32_t)kWave) {
             if (wave == 0) {
