@@ -221,12 +221,19 @@ void build_sample_items(const BatchState &b, std::vector<GemmItem> &items) {
 // the filtered parts (k = kk over their candidate lists), one launch.
 void plan_selects(BatchState &b) {
     b.sample_sel.clear();
+    // a sample row that fits the on-chip capacity is selected there directly
+    // (no pivot sample, no streaming), so short rows go to the class that holds them
+    auto sample_cap = [](const Plan &p) {
+        int c = select_cap_for_k((uint32_t)(p.r + 1));
+        if (p.S > c && p.S <= kSelectKeysCap) c = p.S <= 2048 ? 2048 : 4096;
+        return c;
+    };
     for (int cap : {1024, 2048, 4096}) {
         SegLaunch L;
         L.cap = cap;
         for (const BatchPart &pt : b.parts) {
             const Plan &p = b.jobs[pt.job].p;
-            if (select_cap_for_k((uint32_t)(p.r + 1)) != cap) continue;
+            if (sample_cap(p) != cap) continue;
             SelectSeg sg{};
             sg.dist = pt.Ds;
             sg.ld = p.S;

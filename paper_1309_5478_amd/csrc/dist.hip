@@ -358,27 +358,37 @@ __global__ __launch_bounds__(256) void sqnorm_kernel(const float *__restrict__ X
     const uint32_t lane = lane_id(), sub = lane % G, grp = lane / G, wave = threadIdx.x / kWave;
     const int64_t stride = (int64_t)gridDim.x * (256 / kWave) * PPW;
     float mx = 0.f;
-    for (int64_t base = ((int64_t)blockIdx.x * (256 / kWave) + wave) * PPW; base < n; base += stride) {
-        const int64_t i = base + grp;
-        float acc = 0.f;
-        if (i < n) {
-            const float *x = X + i * d;
-            if (VEC) {
-                for (int t = (int)sub * 4; t < d; t += G * 4) {
-                    const f32x4 v = *reinterpret_cast<const f32x4 *>(x + t);
-                    acc = fmaf(v[0], v[0], acc);
-                    acc = fmaf(v[1], v[1], acc);
-                    acc = fmaf(v[2], v[2], acc);
-                    acc = fmaf(v[3], v[3], acc);
+    // two points per group per step (independent loads in flight)
+    for (int64_t base = ((int64_t)blockIdx.x * (256 / kWave) + wave) * PPW; base < n; base += 2 * stride) {
+        float acc[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int64_t i = base + u * stride + grp;
+            float s = 0.f;
+            if (i < n) {
+                const float *x = X + i * d;
+                if (VEC) {
+                    for (int t = (int)sub * 4; t < d; t += G * 4) {
+                        const f32x4 v = *reinterpret_cast<const f32x4 *>(x + t);
+                        s = fmaf(v[0], v[0], s);
+                        s = fmaf(v[1], v[1], s);
+                        s = fmaf(v[2], v[2], s);
+                        s = fmaf(v[3], v[3], s);
+                    }
+                } else {
+                    for (int t = (int)sub; t < d; t += G) s = fmaf(x[t], x[t], s);
                 }
-            } else {
-                for (int t = (int)sub; t < d; t += G) acc = fmaf(x[t], x[t], acc);
             }
+            acc[u] = s;
         }
 #pragma unroll
-        for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-        if (i < n && sub == 0) out[i] = acc;
-        mx = fmaxf(mx, acc);
+        for (int u = 0; u < 2; ++u) {
+#pragma unroll
+            for (int off = G / 2; off > 0; off >>= 1) acc[u] += __shfl_xor(acc[u], off);
+            const int64_t i = base + u * stride + grp;
+            if (i < n && sub == 0) out[i] = acc[u];
+            mx = fmaxf(mx, acc[u]);
+        }
     }
     if (max_bits) {
 #pragma unroll
@@ -716,7 +726,7 @@ template <int G>
 static void launch_sqnorm_g(const float *X, int64_t n, int d, float *out, unsigned int *max_bits, bool vec,
                             hipStream_t stream) {
     constexpr int PPW = kWave / G;
-    int64_t blocks = (n + 4 * PPW - 1) / (4 * PPW);
+    int64_t blocks = (n + 8 * PPW - 1) / (8 * PPW);
     if (blocks > 4096) blocks = 4096;
     if (vec)
         hipLaunchKernelGGL((sqnorm_kernel<G, true>), dim3((unsigned)blocks), dim3(256), 0, stream, X, n, d, out,

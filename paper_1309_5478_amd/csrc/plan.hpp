@@ -234,7 +234,10 @@ inline Plan make_plan(int64_t m, int64_t n, int d, int k, bool graph, const knn_
         p.S = n < S ? (int)n : (int)S;
         p.gathered = n > p.S;
         p.r = rank_for(p.S, expected);
-        int64_t cap = (int64_t)(2.0 * expected);
+        // the survivor count varies with the sample's order statistic (relative
+        // spread about 1 / sqrt(r + 1)): three times the expectation keeps
+        // overflows (rows re-done exactly) rare
+        int64_t cap = (int64_t)(3.0 * expected);
         if (cap < p.kk + 64) cap = p.kk + 64;
         cap = (cap + 63) / 64 * 64;
         if (cap > kSelectKeysCap) cap = kSelectKeysCap;
