@@ -684,9 +684,10 @@ __global__ void zero_u64_kernel(unsigned long long *p, int n) {
 
 // ---- host side --------------------------------------------------------------
 int select_cap_for_k(uint32_t k) {
-    if (k <= 64) return 1024;
-    if (k <= 256) return 2048;
-    return 4096;
+    // 2048 keys per buffer also for k up to 1024: the first pass keeps about
+    // 2k of a long row, and the rare rows beyond spill to the workspace, which
+    // costs less than the third of the workgroups per CU that 4096 would lose
+    return k <= 64 ? 1024 : 2048;
 }
 
 template <int CAP>
