@@ -315,6 +315,32 @@ __device__ __forceinline__ void load_sample_blocks(SelSmem<CAP> &sm, const float
     __syncthreads();
 }
 
+// The 64 smallest keys of 16 sorted blocks of 64 in sortbuf, ascending, in the
+// lanes of wave 0 (the other waves return kKeyMax): a tree of pairwise merges
+// that keep the lower half (the elementwise minimum of one block and the
+// reverse of the other holds exactly the 64 smallest of the pair, as a bitonic
+// sequence, which six half-cleaning steps sort).  Called by every thread.
+template <int CAP>
+__device__ __forceinline__ uint64_t lowest64_of_blocks(SelSmem<CAP> &sm) {
+    const uint32_t lane = lane_id(), wave = threadIdx.x / kWave;
+    uint64_t m = kKeyMax;
+    for (uint32_t w = 1; w < (uint32_t)kSampleBlocks; w <<= 1) {  // merge width in blocks
+        for (uint32_t q = wave; q < (uint32_t)kSampleBlocks / (2 * w); q += kSelWaves) {
+            const uint32_t a0 = 2 * q * w * kWave, b0 = a0 + w * kWave;
+            const uint64_t x = sm.sortbuf[a0 + lane], y = sm.sortbuf[b0 + (kWave - 1 - lane)];
+            m = x < y ? x : y;
+#pragma unroll
+            for (int st = 32; st > 0; st >>= 1) {
+                const uint64_t o = shfl_xor_u64(m, st);
+                m = (lane & st) ? (o > m ? o : m) : (o < m ? o : m);
+            }
+            if (2 * w < (uint32_t)kSampleBlocks) sm.sortbuf[a0 + lane] = m;
+        }
+        __syncthreads();
+    }
+    return wave == 0 ? m : kKeyMax;
+}
+
 // The r-th smallest (0-based, r < 64) key of 16 sorted blocks of 64 in sortbuf,
 // by an r-step 16-way merge in one wave.  Called by wave 0 only.
 template <int CAP>
@@ -440,9 +466,17 @@ __global__ __launch_bounds__(kSelThreads, (CAP == 1024 && !KEYS) ? 4 : 1) void s
                     load_sample_blocks(sm, row, N);
                     sample_loaded = true;
                     uint32_t rr0 = target_rank(kSortN, k, N, 3.0f, 3.0f);
-                    if (rr0 < (uint32_t)kWave) {
+                    if (rr0 < 8) {  // a few merge steps
                         if (wave == 0) {
                             uint64_t piv = merge_rank(sm, rr0);
+                            if (lane == 0) sm.pivot = piv;
+                        }
+                        __syncthreads();
+                        P = sm.pivot;
+                    } else if (rr0 < (uint32_t)kWave) {  // the merge tree of the lowest 64
+                        const uint64_t low = lowest64_of_blocks(sm);
+                        if (wave == 0) {
+                            const uint64_t piv = wave_readlane_u64(low, (int)rr0);
                             if (lane == 0) sm.pivot = piv;
                         }
                         __syncthreads();
