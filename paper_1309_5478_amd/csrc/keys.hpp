@@ -74,9 +74,37 @@ __device__ __forceinline__ bool key_below(float v, uint32_t j, const Pivot &p) {
     return lt || (eq && j < p.pidx);
 }
 
+// The value of lane (lane ^ mask), every lane of the wave active.  Masks 1, 2
+// and 8 are single DPP moves (quad permutations, a rotation by 8 within rows
+// of 16), mask 4 two row shifts and a select, mask 16 a swizzle within halves
+// of 32; only mask 32 and others go through the LDS crossbar.
+__device__ __forceinline__ uint32_t xor_lanes32(uint32_t v, int mask) {
+    const int x = (int)v;
+    switch (mask) {
+        case 1: return (uint32_t)__builtin_amdgcn_update_dpp(x, x, 0xB1, 0xF, 0xF, false);  // quad_perm 1,0,3,2
+        case 2: return (uint32_t)__builtin_amdgcn_update_dpp(x, x, 0x4E, 0xF, 0xF, false);  // quad_perm 2,3,0,1
+        case 4: {
+            const int up = __builtin_amdgcn_update_dpp(x, x, 0x104, 0xF, 0xF, false);  // row_shl:4, lane + 4
+            const int dn = __builtin_amdgcn_update_dpp(x, x, 0x114, 0xF, 0xF, false);  // row_shr:4, lane - 4
+            return (uint32_t)((lane_id() & 4) ? dn : up);
+        }
+        case 8: return (uint32_t)__builtin_amdgcn_update_dpp(x, x, 0x128, 0xF, 0xF, false);  // row_ror:8
+        case 16: return (uint32_t)__builtin_amdgcn_ds_swizzle(x, 0x401F);                    // xor 16 in 32
+        default: return (uint32_t)__shfl_xor(x, mask);
+    }
+}
+
+// For masks known at compile time (unrolled loops): the DPP forms above.
 __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int mask) {
-    uint32_t lo = __shfl_xor((unsigned int)(uint32_t)v, mask);
-    uint32_t hi = __shfl_xor((unsigned int)(uint32_t)(v >> 32), mask);
+    const uint32_t lo = xor_lanes32((uint32_t)v, mask);
+    const uint32_t hi = xor_lanes32((uint32_t)(v >> 32), mask);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// For masks only known at run time: one LDS-crossbar permute per half.
+__device__ __forceinline__ uint64_t shfl_xor_u64_rt(uint64_t v, int mask) {
+    const uint32_t lo = __shfl_xor((unsigned int)(uint32_t)v, mask);
+    const uint32_t hi = __shfl_xor((unsigned int)(uint32_t)(v >> 32), mask);
     return ((uint64_t)hi << 32) | lo;
 }
 
@@ -158,7 +186,7 @@ __device__ __forceinline__ void block_sort_regs(uint64_t *buf) {
 #pragma unroll
                 for (int j = 0; j < J; ++j) {
                     const uint32_t i = t * J + j;
-                    const uint64_t o = shfl_xor_u64(k[j], ls);
+                    const uint64_t o = shfl_xor_u64_rt(k[j], ls);
                     const bool take_min = ((i & stride) == 0) == ((i & size) == 0);
                     const uint64_t mn = k[j] < o ? k[j] : o, mx = k[j] < o ? o : k[j];
                     k[j] = take_min ? mn : mx;
