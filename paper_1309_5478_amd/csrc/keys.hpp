@@ -164,9 +164,9 @@ __device__ __forceinline__ void block_sort_regs(uint64_t *buf) {
         lo = swap ? b : a;
         hi = swap ? a : b;
     };
-#pragma unroll 1
+#pragma unroll
     for (uint32_t size = 2; size <= N; size <<= 1) {
-#pragma unroll 1
+#pragma unroll
         for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
             if (stride < (uint32_t)J) {
                 if constexpr (J >= 2) {
@@ -186,7 +186,7 @@ __device__ __forceinline__ void block_sort_regs(uint64_t *buf) {
 #pragma unroll
                 for (int j = 0; j < J; ++j) {
                     const uint32_t i = t * J + j;
-                    const uint64_t o = shfl_xor_u64_rt(k[j], ls);
+                    const uint64_t o = shfl_xor_u64(k[j], ls);
                     const bool take_min = ((i & stride) == 0) == ((i & size) == 0);
                     const uint64_t mn = k[j] < o ? k[j] : o, mx = k[j] < o ? o : k[j];
                     k[j] = take_min ? mn : mx;
