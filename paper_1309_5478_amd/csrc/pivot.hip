@@ -32,9 +32,9 @@ __global__ __launch_bounds__(kFeatThreads) void net_features_kernel(const float 
     for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
         const float *row = D + r * ld;
         const uint32_t j = net_sample_start(wave, N) + lane;
-        keys[tid] = wave_sort64(make_key(row[j], j));
+        keys[tid] = make_key(row[j], j);
         __syncthreads();
-        block_merge_runs<kFeatThreads>(keys, kNetSample, kWave);
+        block_sort<kFeatThreads>(keys, kNetSample);
         v[tid] = ord_to_float(key_ord(keys[tid]));
         __syncthreads();
         if (wave == 0) {

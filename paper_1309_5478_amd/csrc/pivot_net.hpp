@@ -90,35 +90,4 @@ __device__ __forceinline__ float net_forward_wave(const uint16_t *__restrict__ w
     return y + bf16_to_f32(w[kOffB3]);
 }
 
-// Ascending sort of n keys in LDS made of sorted runs of length `run` (a power
-// of two), by merging pairs of runs: the first stage of each level compares
-// element i with its mirror in the merged block, the others are half-cleaners.
-template <int NT>
-__device__ __forceinline__ void block_merge_runs(uint64_t *buf, uint32_t n, uint32_t run) {
-    for (uint32_t size = 2 * run; size <= n; size <<= 1) {
-        const uint32_t half = size >> 1;
-        for (uint32_t t = threadIdx.x; t < (n >> 1); t += NT) {
-            const uint32_t blk = t / half, i = t % half;
-            const uint32_t a = blk * size + i, b = blk * size + size - 1 - i;
-            uint64_t x = buf[a], y = buf[b];
-            if (x > y) {
-                buf[a] = y;
-                buf[b] = x;
-            }
-        }
-        __syncthreads();
-        for (uint32_t stride = half >> 1; stride > 0; stride >>= 1) {
-            for (uint32_t t = threadIdx.x; t < (n >> 1); t += NT) {
-                const uint32_t lo = 2 * t - (t & (stride - 1)), hi = lo + stride;
-                uint64_t x = buf[lo], y = buf[hi];
-                if (x > y) {
-                    buf[lo] = y;
-                    buf[hi] = x;
-                }
-            }
-            __syncthreads();
-        }
-    }
-}
-
 }  // namespace knn

@@ -372,11 +372,19 @@ __global__ __launch_bounds__(kSelThreads, (CAP == 1024 && !KEYS) ? 4 : 1) void s
     SelectArgs a, uint64_t *ws, uint64_t ws_slot) {
     __shared__ SelSmem<CAP> sm;
     static_assert(sizeof(sm.buf) >= (size_t)(kNetParams + 1) * 2, "partition buffers must hold the pivot network");
+    // the pivot network's weights, staged once per workgroup where the LDS
+    // budget allows (otherwise per row, in the still unused partition buffers)
+    constexpr bool kOwnNet = !KEYS && CAP <= 2048;
+    __shared__ uint32_t net_lds[kOwnNet ? (kNetParams + 1) / 2 : 1];
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
     GBuf gb{ws + (uint64_t)blockIdx.x * 2 * ws_slot, ws + (uint64_t)blockIdx.x * 2 * ws_slot + ws_slot};
 
     // per-workgroup totals of the row statistics, in LDS (kept by thread 0)
     if (tid < kAccSlots) sm.acc[tid] = 0;
+    if (kOwnNet && a.mode == kPivotLearned && a.net) {
+        const uint32_t *wg = reinterpret_cast<const uint32_t *>(a.net);
+        for (uint32_t t = tid; t < (uint32_t)(kNetParams + 1) / 2; t += kSelThreads) net_lds[t] = wg[t];
+    }
     __syncthreads();
     for (int64_t r = blockIdx.x; r < a.rows; r += gridDim.x) {
         // this row's matrix: the launch's own, or one segment of several
@@ -438,16 +446,19 @@ __global__ __launch_bounds__(kSelThreads, (CAP == 1024 && !KEYS) ? 4 : 1) void s
                     // learned: 4 sample blocks (one per wave) -> features -> network
                     {
                         const uint32_t j = net_sample_start(wave, N) + lane;
-                        sm.sortbuf[tid] = wave_sort64(make_key(row[j], j));
+                        sm.sortbuf[tid] = make_key(row[j], j);
                     }
                     __syncthreads();
-                    block_merge_runs<kSelThreads>(sm.sortbuf, kNetSample, kWave);
+                    block_sort<kSelThreads>(sm.sortbuf, kNetSample);
                     float *vf = reinterpret_cast<float *>(sm.sortbuf + kNetSample);
                     vf[tid] = ord_to_float(key_ord(sm.sortbuf[tid]));
-                    // the BF16 weights, staged in the (still unused) partition buffers
-                    uint32_t *wl = reinterpret_cast<uint32_t *>(&sm.buf[0][0]);
-                    const uint32_t *wg = reinterpret_cast<const uint32_t *>(a.net);
-                    for (uint32_t t = tid; t < (uint32_t)(kNetParams + 1) / 2; t += kSelThreads) wl[t] = wg[t];
+                    // the BF16 weights: staged once per workgroup, or now in the
+                    // (still unused) partition buffers
+                    uint32_t *wl = kOwnNet ? net_lds : reinterpret_cast<uint32_t *>(&sm.buf[0][0]);
+                    if (!kOwnNet) {
+                        const uint32_t *wg = reinterpret_cast<const uint32_t *>(a.net);
+                        for (uint32_t t = tid; t < (uint32_t)(kNetParams + 1) / 2; t += kSelThreads) wl[t] = wg[t];
+                    }
                     __syncthreads();
                     if (wave == 0) {
                         float x[kNetIn], m, s;

@@ -182,3 +182,26 @@ def test_tile_shapes_give_identical_bits(h, torch, prec):
     for tile, o in outs.items():
         for a, b in zip(o, ref):
             assert np.array_equal(a, b), (prec, tile)
+
+
+def test_autotuned_tile_gives_identical_bits(h, torch, tmp_path):
+    """KNN_FLAG_AUTOTUNE times the tile shapes on the call's operands (with a
+    threshold that keeps nothing), records the choice in the cache file and
+    returns the same bits as the default shape."""
+    import os
+    import paper_1309_5478_amd as knn
+    P = synth.gmm_points(6000, 96, seed=synth.SEEDS["knng_small"] + 60)
+    dev = torch.from_numpy(P).cuda()
+    base = h.graph(dev, 12)
+    path = str(tmp_path / "tune.json")
+    os.environ["KNN_AUTOTUNE_CACHE"] = path
+    try:
+        tuned = h.graph(dev, 12, flags=knn.FLAG_AUTOTUNE)
+        again = h.graph(dev, 12, flags=knn.FLAG_AUTOTUNE)   # cached choice
+        torch.cuda.synchronize()
+        assert "fused|" in open(path).read()
+    finally:
+        del os.environ["KNN_AUTOTUNE_CACHE"]
+    for got in (tuned, again):
+        assert np.array_equal(got[1].cpu().numpy(), base[1].cpu().numpy())
+        assert np.array_equal(got[0].cpu().numpy().view(np.uint32), base[0].cpu().numpy().view(np.uint32))
