@@ -66,6 +66,8 @@ struct SelectArgs {
 
 // Largest k a selection call supports.
 constexpr int kSelectMaxK = 1024;
+// LDS partition buffer size (keys) of the distance-matrix selection
+constexpr int kSelectCap = 1024;
 
 // Capacity class (keys held on chip per buffer) used for a given k.
 int select_cap_for_k(uint32_t k);

@@ -81,14 +81,14 @@ __device__ __forceinline__ bool key_below(float v, uint32_t j, const Pivot &p) {
 __device__ __forceinline__ uint32_t xor_lanes32(uint32_t v, int mask) {
     const int x = (int)v;
     switch (mask) {
-        case 1: return (uint32_t)__builtin_amdgcn_update_dpp(x, x, 0xB1, 0xF, 0xF, false);  // quad_perm 1,0,3,2
-        case 2: return (uint32_t)__builtin_amdgcn_update_dpp(x, x, 0x4E, 0xF, 0xF, false);  // quad_perm 2,3,0,1
+        case 1: return (uint32_t)__builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false);  // quad_perm 1,0,3,2
+        case 2: return (uint32_t)__builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, false);  // quad_perm 2,3,0,1
         case 4: {
-            const int up = __builtin_amdgcn_update_dpp(x, x, 0x104, 0xF, 0xF, false);  // row_shl:4, lane + 4
-            const int dn = __builtin_amdgcn_update_dpp(x, x, 0x114, 0xF, 0xF, false);  // row_shr:4, lane - 4
+            const int up = __builtin_amdgcn_mov_dpp(x, 0x104, 0xF, 0xF, false);  // row_shl:4, lane + 4
+            const int dn = __builtin_amdgcn_mov_dpp(x, 0x114, 0xF, 0xF, false);  // row_shr:4, lane - 4
             return (uint32_t)((lane_id() & 4) ? dn : up);
         }
-        case 8: return (uint32_t)__builtin_amdgcn_update_dpp(x, x, 0x128, 0xF, 0xF, false);  // row_ror:8
+        case 8: return (uint32_t)__builtin_amdgcn_mov_dpp(x, 0x128, 0xF, 0xF, false);  // row_ror:8
         case 16: return (uint32_t)__builtin_amdgcn_ds_swizzle(x, 0x401F);                    // xor 16 in 32
         default: return (uint32_t)__shfl_xor(x, mask);
     }
@@ -128,13 +128,9 @@ __device__ __forceinline__ uint64_t wave_sort64(uint64_t key) {
     for (int size = 2; size <= kWave; size <<= 1) {
 #pragma unroll
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            uint64_t other = shfl_xor_u64(key, stride);
-            bool up = (lane & size) == 0;
-            bool lower = (lane & stride) == 0;
-            bool take_min = (lower == up);
-            uint64_t mn = key < other ? key : other;
-            uint64_t mx = key < other ? other : key;
-            key = take_min ? mn : mx;
+            const uint64_t other = shfl_xor_u64(key, stride);
+            const bool take_min = ((lane & stride) == 0) == ((lane & size) == 0);
+            key = ((key < other) == take_min) ? key : other;
         }
     }
     return key;
@@ -146,7 +142,7 @@ __device__ __forceinline__ uint64_t wave_readlane_u64(uint64_t v, int lane) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-// Ascending bitonic sort of NT * J keys of buf (J = 1, 2 or 4), with the keys
+// Ascending bitonic sort of NT * J keys of buf (J = 1, 2, 4 or 8), with the keys
 // in registers: thread t holds keys t*J .. t*J + J - 1, so compare-exchange
 // partners less than J apart are in the same thread, partners less than 64*J
 // apart are in the same wave (one shuffle), and only the strides of J*64 and
@@ -169,41 +165,31 @@ __device__ __forceinline__ void block_sort_regs(uint64_t *buf) {
 #pragma unroll
         for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
             if (stride < (uint32_t)J) {
-                if constexpr (J >= 2) {
-                    if (stride == 1) {
 #pragma unroll
-                        for (int j = 0; j < J; j += 2) cas(k[j], k[j + 1], ((t * J + j) & size) == 0);
-                    }
-                }
-                if constexpr (J >= 4) {
-                    if (stride == 2) {
-#pragma unroll
-                        for (int j = 0; j < 2; ++j) cas(k[j], k[j + 2], ((t * J + j) & size) == 0);
-                    }
-                }
-            } else if (stride < (uint32_t)J * kWave) {
-                const int ls = (int)(stride / J);
-#pragma unroll
-                for (int j = 0; j < J; ++j) {
-                    const uint32_t i = t * J + j;
-                    const uint64_t o = shfl_xor_u64(k[j], ls);
-                    const bool take_min = ((i & stride) == 0) == ((i & size) == 0);
-                    const uint64_t mn = k[j] < o ? k[j] : o, mx = k[j] < o ? o : k[j];
-                    k[j] = take_min ? mn : mx;
-                }
+                for (int j = 0; j < J; ++j)
+                    if ((j & stride) == 0) cas(k[j], k[j + stride], ((t * J + j) & size) == 0);
             } else {
+                // partners in other threads: the direction is the same for all J
+                // keys of a thread (stride and size are multiples of J), and a
+                // key stays where it is exactly when it is already on the side
+                // its direction asks for (one compare and one select per key)
+                const uint32_t i0 = t * J;
+                const bool take_min = ((i0 & stride) == 0) == ((i0 & size) == 0);
+                uint64_t o[J];
+                if (stride < (uint32_t)J * kWave) {
+                    const int ls = (int)(stride / J);
 #pragma unroll
-                for (int j = 0; j < J; ++j) buf[t * J + j] = k[j];
-                __syncthreads();
+                    for (int j = 0; j < J; ++j) o[j] = shfl_xor_u64(k[j], ls);
+                } else {
 #pragma unroll
-                for (int j = 0; j < J; ++j) {
-                    const uint32_t i = t * J + j;
-                    const uint64_t o = buf[i ^ stride];
-                    const bool take_min = ((i & stride) == 0) == ((i & size) == 0);
-                    const uint64_t mn = k[j] < o ? k[j] : o, mx = k[j] < o ? o : k[j];
-                    k[j] = take_min ? mn : mx;
+                    for (int j = 0; j < J; ++j) buf[i0 + j] = k[j];
+                    __syncthreads();
+#pragma unroll
+                    for (int j = 0; j < J; ++j) o[j] = buf[(i0 + j) ^ stride];
+                    __syncthreads();
                 }
-                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < J; ++j) k[j] = ((k[j] < o[j]) == take_min) ? k[j] : o[j];
             }
         }
     }
@@ -212,20 +198,24 @@ __device__ __forceinline__ void block_sort_regs(uint64_t *buf) {
     __syncthreads();
 }
 
-// Ascending sort of the first n keys of buf (n <= 4 * NT): pads to NT, 2 NT or
-// 4 NT keys with the largest key, then sorts in registers (the buffer must
-// hold the padded length).  Callers have made the n keys visible (barrier).
-template <int NT>
+// Ascending sort of the first n keys of buf (n <= MAXJ * NT, MAXJ = 4 or 8):
+// pads to the next of NT, 2 NT, 4 NT (, 8 NT) keys with the largest key, then
+// sorts in registers (the buffer must hold the padded length).  Callers have
+// made the n keys visible (barrier).
+template <int NT, int MAXJ = 4>
 __device__ __forceinline__ void block_sort(uint64_t *buf, uint32_t n) {
-    const uint32_t m = n <= (uint32_t)NT ? NT : (n <= 2u * NT ? 2 * NT : 4 * NT);
+    static_assert(MAXJ == 4 || MAXJ == 8, "4 or 8 keys per thread at most");
+    const uint32_t m = n <= (uint32_t)NT ? NT : (n <= 2u * NT ? 2 * NT : (n <= 4u * NT ? 4 * NT : 8 * NT));
     for (uint32_t t = n + threadIdx.x; t < m; t += NT) buf[t] = kKeyMax;
     __syncthreads();
     if (m == (uint32_t)NT)
         block_sort_regs<NT, 1>(buf);
     else if (m == 2u * NT)
         block_sort_regs<NT, 2>(buf);
-    else
+    else if (MAXJ == 4 || m == 4u * NT)
         block_sort_regs<NT, 4>(buf);
+    else
+        block_sort_regs<NT, MAXJ>(buf);
 }
 
 }  // namespace knn

@@ -332,7 +332,7 @@ __device__ __forceinline__ uint64_t lowest64_of_blocks(SelSmem<CAP> &sm) {
 #pragma unroll
             for (int st = 32; st > 0; st >>= 1) {
                 const uint64_t o = shfl_xor_u64(m, st);
-                m = (lane & st) ? (o > m ? o : m) : (o < m ? o : m);
+                m = ((m < o) == ((lane & st) == 0)) ? m : o;
             }
             if (2 * w < (uint32_t)kSampleBlocks) sm.sortbuf[a0 + lane] = m;
         }
@@ -365,16 +365,38 @@ __device__ __forceinline__ uint64_t merge_rank(SelSmem<CAP> &sm, uint32_t r) {
     return mn;
 }
 
-// The CAP = 1024 instance (k <= 64) is held to 128 registers so that four
-// workgroups share a CU (its LDS allows it); the others are limited by LDS.
+// Finishing by one sort of the active segment in place: possible while nothing
+// has been kept aside (so the answer is the segment's k smallest) and the
+// segment lies wholly in LDS; chosen once it is at most 4 keys per thread, or 8
+// where the buffer holds them and so many keys are still needed that another
+// partition pass would shrink it by little.  Rows with k <= 64 finish in one
+// wave instead.
+template <int CAP>
+constexpr int kDirectMaxJ = CAP >= 8 * kSelThreads ? 8 : 4;
+constexpr uint32_t kDirectMinK = kWave;
+constexpr uint32_t kDirectWideK = 512;
+
+template <int CAP>
+__device__ __forceinline__ bool direct_sort_fits(uint32_t nstack, uint32_t ss, uint32_t se, uint32_t Kp, uint32_t k) {
+    const uint32_t len = se - ss;
+    if (nstack != 0 || ss != 0 || Kp != k || se > (uint32_t)CAP || Kp <= kDirectMinK) return false;
+    if (len <= 4u * kSelThreads) return true;
+    return kDirectMaxJ<CAP> == 8 && len <= 8u * kSelThreads && Kp >= kDirectWideK;
+}
+
+// The distance-matrix instance (CAP = 1024, about 26 KB of LDS) is held to 96
+// registers so that five workgroups share a CU: with every phase of a row but
+// the stream latency-bound, more rows in flight per CU pay for the few
+// per-row register reloads and for the longer rows that overflow to the
+// workspace.  The larger instances serve rows that fit them whole.
 template <int CAP, bool KEYS>
-__global__ __launch_bounds__(kSelThreads, (CAP == 1024 && !KEYS) ? 4 : 1) void select_rows_kernel(
+__global__ __launch_bounds__(kSelThreads, (CAP == kSelectCap && !KEYS) ? 5 : 1) void select_rows_kernel(
     SelectArgs a, uint64_t *ws, uint64_t ws_slot) {
     __shared__ SelSmem<CAP> sm;
     static_assert(sizeof(sm.buf) >= (size_t)(kNetParams + 1) * 2, "partition buffers must hold the pivot network");
     // the pivot network's weights, staged once per workgroup where the LDS
     // budget allows (otherwise per row, in the still unused partition buffers)
-    constexpr bool kOwnNet = !KEYS && CAP <= 2048;
+    constexpr bool kOwnNet = !KEYS && CAP >= 2048;
     __shared__ uint32_t net_lds[kOwnNet ? (kNetParams + 1) / 2 : 1];
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
     GBuf gb{ws + (uint64_t)blockIdx.x * 2 * ws_slot, ws + (uint64_t)blockIdx.x * 2 * ws_slot + ws_slot};
@@ -559,13 +581,19 @@ __global__ __launch_bounds__(kSelThreads, (CAP == 1024 && !KEYS) ? 4 : 1) void s
             cyc_stream += clock64() - t1;
         }
 
-        // 3. quickselect passes over the active segment
+        // 3. quickselect passes over the active segment, until it is short
+        // enough to be sorted where it lies
         long long t2 = clock64();
         uint32_t nfinal = 0;
+        bool direct = false;
         for (;;) {
             uint32_t len = se - ss;
             if (Kp == len) {
                 push_seg(sm, gb, sb, ss, se, nstack, agg, true);
+                break;
+            }
+            if (direct_sort_fits<CAP>(nstack, ss, se, Kp, k)) {
+                direct = true;
                 break;
             }
             if (passes >= (uint32_t)kMaxPasses) {
@@ -610,10 +638,12 @@ __global__ __launch_bounds__(kSelThreads, (CAP == 1024 && !KEYS) ? 4 : 1) void s
 
         // 4. gather kept keys, sort, write out
         long long t3 = clock64();
-        agg = flush_stack(sm, gb, nstack, agg);
-        for (uint32_t t = tid; t < nfinal; t += kSelThreads) sm.sortbuf[agg + t] = sm.finals[t];
-        agg += nfinal;
-        __syncthreads();
+        if (!direct) {
+            agg = flush_stack(sm, gb, nstack, agg);
+            for (uint32_t t = tid; t < nfinal; t += kSelThreads) sm.sortbuf[agg + t] = sm.finals[t];
+            agg += nfinal;
+            __syncthreads();
+        }
         // (agg == k on every normal exit)
         auto emit = [&](uint32_t t, uint64_t key) {
             uint32_t idx = key_idx(key), o = key_ord(key);
@@ -627,7 +657,14 @@ __global__ __launch_bounds__(kSelThreads, (CAP == 1024 && !KEYS) ? 4 : 1) void s
             out_val[lr * k + t] = v;
             out_idx[lr * k + t] = (int32_t)idx;
         };
-        if (k <= (uint32_t)kWave) {
+        if (direct) {
+            // no kept segments: the active segment [0, len) of buffer sb holds
+            // every key below its upper end, and its first k after sorting are
+            // the answer
+            uint64_t *seg = sb ? &sm.buf[1][0] : &sm.buf[0][0];
+            block_sort<kSelThreads, kDirectMaxJ<CAP>>(seg, se);
+            for (uint32_t t = tid; t < k; t += kSelThreads) emit(t, seg[t]);
+        } else if (k <= (uint32_t)kWave) {
             if (wave == 0) {
                 uint64_t key = wave_sort64(lane < agg ? sm.sortbuf[lane] : kKeyMax);
                 if (lane < k) emit(lane, key);
@@ -729,10 +766,12 @@ __global__ void zero_u64_kernel(unsigned long long *p, int n) {
 
 // ---- host side --------------------------------------------------------------
 int select_cap_for_k(uint32_t k) {
-    // 2048 keys per buffer also for k up to 1024: the first pass keeps about
-    // 2k of a long row, and the rare rows beyond spill to the workspace, which
-    // costs less than the third of the workgroups per CU that 4096 would lose
-    return k <= 64 ? 1024 : 2048;
+    // 1024 keys per buffer for every k: the first pass keeps about 2k of a long
+    // row, and the part beyond the LDS buffer goes to the workspace (mostly L2
+    // hits); that costs less than the fifth to half of the workgroups per CU
+    // that larger buffers would take away
+    (void)k;
+    return kSelectCap;
 }
 
 template <int CAP>
@@ -749,7 +788,7 @@ static int blocks_per_cu() {
 }
 
 int select_grid(int cap, int64_t rows, int num_cu) {
-    int per = cap == 1024 ? blocks_per_cu<1024>() : cap == 2048 ? blocks_per_cu<2048>() : blocks_per_cu<4096>();
+    int per = cap == 2048 ? blocks_per_cu<2048>() : cap == 4096 ? blocks_per_cu<4096>() : blocks_per_cu<kSelectCap>();
     int64_t g = (int64_t)per * num_cu;
     if (g > rows) g = rows;
     return g < 1 ? 1 : (int)g;
@@ -764,7 +803,10 @@ hipError_t launch_select(const SelectArgs &a, int cap, int grid, void *ws, hipSt
     uint64_t slot = a.cols > (uint32_t)cap ? (uint64_t)a.cols - cap : 0;
     uint64_t *w = static_cast<uint64_t *>(ws);
     switch (cap) {
-        case 1024: hipLaunchKernelGGL((select_rows_kernel<1024, false>), dim3(grid), dim3(kSelThreads), 0, stream, a, w, slot); break;
+        case kSelectCap:
+            hipLaunchKernelGGL((select_rows_kernel<kSelectCap, false>), dim3(grid), dim3(kSelThreads), 0, stream, a, w,
+                               slot);
+            break;
         case 2048: hipLaunchKernelGGL((select_rows_kernel<2048, false>), dim3(grid), dim3(kSelThreads), 0, stream, a, w, slot); break;
         case 4096: hipLaunchKernelGGL((select_rows_kernel<4096, false>), dim3(grid), dim3(kSelThreads), 0, stream, a, w, slot); break;
         default: return hipErrorInvalidValue;
