@@ -147,13 +147,18 @@ __device__ __forceinline__ uint64_t wave_readlane_u64(uint64_t v, int lane) {
 // partners less than J apart are in the same thread, partners less than 64*J
 // apart are in the same wave (one shuffle), and only the strides of J*64 and
 // above go through LDS, with a barrier each.
-template <int NT, int J>
-__device__ __forceinline__ void block_sort_regs(uint64_t *buf) {
+//
+// The keys come from load(i) for i in [0, NT * J); buf is the exchange area and
+// receives the sorted keys.  With SYNC the threads wait for each other after
+// loading (needed when load reads LDS that other threads overwrite).
+template <int NT, int J, bool SYNC, class Load>
+__device__ __forceinline__ void block_sort_regs_from(uint64_t *buf, Load load) {
     constexpr uint32_t N = (uint32_t)NT * J;
     const uint32_t t = threadIdx.x;
     uint64_t k[J];
 #pragma unroll
-    for (int j = 0; j < J; ++j) k[j] = buf[t * J + j];
+    for (int j = 0; j < J; ++j) k[j] = load(t * J + j);
+    if (SYNC) __syncthreads();
     auto cas = [](uint64_t &lo, uint64_t &hi, bool up) {
         const uint64_t a = lo, b = hi;
         const bool swap = (a > b) == up;
@@ -196,6 +201,12 @@ __device__ __forceinline__ void block_sort_regs(uint64_t *buf) {
 #pragma unroll
     for (int j = 0; j < J; ++j) buf[t * J + j] = k[j];
     __syncthreads();
+}
+
+// In place: every thread loads exactly the positions it later writes.
+template <int NT, int J>
+__device__ __forceinline__ void block_sort_regs(uint64_t *buf) {
+    block_sort_regs_from<NT, J, false>(buf, [buf](uint32_t i) { return buf[i]; });
 }
 
 // Ascending sort of the first n keys of buf (n <= MAXJ * NT, MAXJ = 4 or 8):

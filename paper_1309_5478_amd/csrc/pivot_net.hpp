@@ -68,26 +68,40 @@ __device__ __forceinline__ void net_features(const float *v, uint32_t N, uint32_
     x[7] = logf(s / (fabsf(m) + s));
 }
 
-// Forward pass by one wave; x is uniform across the wave.  Weights are BF16,
-// accumulation FP32 in a fixed order.  Returns y_hat in every lane.
+// Forward pass by one wave; x is uniform across the wave.  Weights are BF16
+// (w 4-byte aligned, global memory or LDS), accumulation FP32 in a fixed order.
+// Each lane loads its unit's weight rows up front, so that all the loads are in
+// flight together.  Returns y_hat in every lane.
 __device__ __forceinline__ float net_forward_wave(const uint16_t *__restrict__ w, const float x[kNetIn]) {
     const uint32_t j = lane_id();
-    float z1 = bf16_to_f32(w[kOffB1 + j]);
+    const uint32_t *w1 = reinterpret_cast<const uint32_t *>(w + kOffW1 + j * kNetIn);
+    const uint32_t *w2 = reinterpret_cast<const uint32_t *>(w + kOffW2 + j * kNetHidden);
+    uint32_t r1[kNetIn / 2], r2[kNetHidden / 2];
 #pragma unroll
-    for (int i = 0; i < kNetIn; ++i) z1 = fmaf(bf16_to_f32(w[kOffW1 + j * kNetIn + i]), x[i], z1);
+    for (int i = 0; i < kNetIn / 2; ++i) r1[i] = w1[i];
+#pragma unroll
+    for (int i = 0; i < kNetHidden / 2; ++i) r2[i] = w2[i];
+    const float b1 = bf16_to_f32(w[kOffB1 + j]), b2 = bf16_to_f32(w[kOffB2 + j]);
+    const float w3 = bf16_to_f32(w[kOffW3 + j]), b3 = bf16_to_f32(w[kOffB3]);
+    // element i of a packed row: the low half of word i / 2 for even i
+    auto elem = [](const uint32_t *r, int i) {
+        return __uint_as_float((i & 1) ? (r[i >> 1] & 0xFFFF0000u) : (r[i >> 1] << 16));
+    };
+    float z1 = b1;
+#pragma unroll
+    for (int i = 0; i < kNetIn; ++i) z1 = fmaf(elem(r1, i), x[i], z1);
     const float h1 = z1 > 0.f ? z1 : 0.f;
-    float z2 = bf16_to_f32(w[kOffB2 + j]);
-    const uint16_t *row = w + kOffW2 + j * kNetHidden;
-#pragma unroll 8
+    float z2 = b2;
+#pragma unroll
     for (int i = 0; i < kNetHidden; ++i) {
         const float hi = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(h1), i));  // h1 of unit i
-        z2 = fmaf(bf16_to_f32(row[i]), hi, z2);
+        z2 = fmaf(elem(r2, i), hi, z2);
     }
     const float h2 = z2 > 0.f ? z2 : 0.f;
-    float y = bf16_to_f32(w[kOffW3 + j]) * h2;
+    float y = w3 * h2;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) y += __shfl_xor(y, off);
-    return y + bf16_to_f32(w[kOffB3]);
+    return y + b3;
 }
 
 }  // namespace knn

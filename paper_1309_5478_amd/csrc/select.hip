@@ -365,23 +365,22 @@ __device__ __forceinline__ uint64_t merge_rank(SelSmem<CAP> &sm, uint32_t r) {
     return mn;
 }
 
-// Finishing by one sort of the active segment in place: possible while nothing
-// has been kept aside (so the answer is the segment's k smallest) and the
-// segment lies wholly in LDS; chosen once it is at most 4 keys per thread, or 8
-// where the buffer holds them and so many keys are still needed that another
-// partition pass would shrink it by little.  Rows with k <= 64 finish in one
-// wave instead.
-template <int CAP>
-constexpr int kDirectMaxJ = CAP >= 8 * kSelThreads ? 8 : 4;
+// Finishing by one register sort of the active segment: possible while nothing
+// has been kept aside (so the answer is the segment's k smallest); chosen once
+// the segment is at most 4 keys per thread, or 8 when so many keys are still
+// needed that another partition pass would shrink it by little.  The sort
+// exchanges keys through both LDS buffers (2 CAP >= 8 x 256 keys).  Rows with
+// k <= 64 finish in one wave instead.
 constexpr uint32_t kDirectMinK = kWave;
 constexpr uint32_t kDirectWideK = 512;
 
 template <int CAP>
 __device__ __forceinline__ bool direct_sort_fits(uint32_t nstack, uint32_t ss, uint32_t se, uint32_t Kp, uint32_t k) {
+    static_assert(2 * CAP >= 8 * kSelThreads, "exchange area");
     const uint32_t len = se - ss;
-    if (nstack != 0 || ss != 0 || Kp != k || se > (uint32_t)CAP || Kp <= kDirectMinK) return false;
+    if (nstack != 0 || ss != 0 || Kp != k || Kp <= kDirectMinK) return false;
     if (len <= 4u * kSelThreads) return true;
-    return kDirectMaxJ<CAP> == 8 && len <= 8u * kSelThreads && Kp >= kDirectWideK;
+    return len <= 8u * kSelThreads && Kp >= kDirectWideK;
 }
 
 // The distance-matrix instance (CAP = 1024, about 26 KB of LDS) is held to 96
@@ -393,20 +392,11 @@ template <int CAP, bool KEYS>
 __global__ __launch_bounds__(kSelThreads, (CAP == kSelectCap && !KEYS) ? 5 : 1) void select_rows_kernel(
     SelectArgs a, uint64_t *ws, uint64_t ws_slot) {
     __shared__ SelSmem<CAP> sm;
-    static_assert(sizeof(sm.buf) >= (size_t)(kNetParams + 1) * 2, "partition buffers must hold the pivot network");
-    // the pivot network's weights, staged once per workgroup where the LDS
-    // budget allows (otherwise per row, in the still unused partition buffers)
-    constexpr bool kOwnNet = !KEYS && CAP >= 2048;
-    __shared__ uint32_t net_lds[kOwnNet ? (kNetParams + 1) / 2 : 1];
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
     GBuf gb{ws + (uint64_t)blockIdx.x * 2 * ws_slot, ws + (uint64_t)blockIdx.x * 2 * ws_slot + ws_slot};
 
     // per-workgroup totals of the row statistics, in LDS (kept by thread 0)
     if (tid < kAccSlots) sm.acc[tid] = 0;
-    if (kOwnNet && a.mode == kPivotLearned && a.net) {
-        const uint32_t *wg = reinterpret_cast<const uint32_t *>(a.net);
-        for (uint32_t t = tid; t < (uint32_t)(kNetParams + 1) / 2; t += kSelThreads) net_lds[t] = wg[t];
-    }
     __syncthreads();
     for (int64_t r = blockIdx.x; r < a.rows; r += gridDim.x) {
         // this row's matrix: the launch's own, or one segment of several
@@ -474,18 +464,11 @@ __global__ __launch_bounds__(kSelThreads, (CAP == kSelectCap && !KEYS) ? 5 : 1) 
                     block_sort<kSelThreads>(sm.sortbuf, kNetSample);
                     float *vf = reinterpret_cast<float *>(sm.sortbuf + kNetSample);
                     vf[tid] = ord_to_float(key_ord(sm.sortbuf[tid]));
-                    // the BF16 weights: staged once per workgroup, or now in the
-                    // (still unused) partition buffers
-                    uint32_t *wl = kOwnNet ? net_lds : reinterpret_cast<uint32_t *>(&sm.buf[0][0]);
-                    if (!kOwnNet) {
-                        const uint32_t *wg = reinterpret_cast<const uint32_t *>(a.net);
-                        for (uint32_t t = tid; t < (uint32_t)(kNetParams + 1) / 2; t += kSelThreads) wl[t] = wg[t];
-                    }
                     __syncthreads();
                     if (wave == 0) {
                         float x[kNetIn], m, s;
                         net_features(vf, N, k, x, m, s);
-                        const float y = net_forward_wave(reinterpret_cast<const uint16_t *>(wl), x);
+                        const float y = net_forward_wave(a.net, x);  // BF16 weights, read from global memory
                         if (lane == 0) sm.pivot = (uint64_t)__float_as_uint(fmaf(s, y, m));
                     }
                     __syncthreads();
@@ -658,12 +641,22 @@ __global__ __launch_bounds__(kSelThreads, (CAP == kSelectCap && !KEYS) ? 5 : 1) 
             out_idx[lr * k + t] = (int32_t)idx;
         };
         if (direct) {
-            // no kept segments: the active segment [0, len) of buffer sb holds
-            // every key below its upper end, and its first k after sorting are
-            // the answer
-            uint64_t *seg = sb ? &sm.buf[1][0] : &sm.buf[0][0];
-            block_sort<kSelThreads, kDirectMaxJ<CAP>>(seg, se);
-            for (uint32_t t = tid; t < k; t += kSelThreads) emit(t, seg[t]);
+            // no kept segments: the active segment [0, se) of buffer sb (its
+            // tail possibly in the workspace) holds every key below its upper
+            // end, and its first k after sorting are the answer; both LDS
+            // buffers together are the sort's exchange area
+            uint64_t *xb = &sm.buf[0][0];
+            const uint32_t len = se;
+            auto load = [&](uint32_t p) { return p < len ? vld(sm, gb, sb, p) : kKeyMax; };
+            if (len <= (uint32_t)kSelThreads)
+                block_sort_regs_from<kSelThreads, 1, true>(xb, load);
+            else if (len <= 2u * kSelThreads)
+                block_sort_regs_from<kSelThreads, 2, true>(xb, load);
+            else if (len <= 4u * kSelThreads)
+                block_sort_regs_from<kSelThreads, 4, true>(xb, load);
+            else
+                block_sort_regs_from<kSelThreads, 8, true>(xb, load);
+            for (uint32_t t = tid; t < k; t += kSelThreads) emit(t, xb[t]);
         } else if (k <= (uint32_t)kWave) {
             if (wave == 0) {
                 uint64_t key = wave_sort64(lane < agg ? sm.sortbuf[lane] : kKeyMax);
