@@ -505,7 +505,7 @@ hipError_t enqueue_final(const BatchState &b, knn_handle_t h, int num_cu, hipStr
     // the kk smallest candidate keys of every filtered row, one launch
     if (b.keys_sel.rows) {
         SelectArgs ka = seg_select_args(b, b.keys_sel);
-        BTRY(launch_select_keys(ka, ka.rows, num_cu, s));
+        BTRY(launch_select_keys(ka, b.sh.selws, ka.rows, num_cu, s));
     }
     for (const BatchPart &pt : b.parts) {
         if (pt.direct) continue;

@@ -62,6 +62,8 @@ struct SelectArgs {
     // the segments
     const SelectSeg *segs;
     const uint32_t *row_seg;
+    // row counter for dynamic row claiming (set by launch_select), or null
+    unsigned long long *next_row;
 };
 
 // Largest k a selection call supports.
@@ -79,7 +81,10 @@ size_t select_ws_bytes(int cap, uint32_t cols, int grid);
 hipError_t launch_select(const SelectArgs &a, int cap, int grid, void *ws, hipStream_t stream);
 // Selection over key-list rows (a.keys / a.key_cnt set, a.cols <= kSelectKeysCap).
 constexpr int kSelectKeysCap = 4096;
-hipError_t launch_select_keys(const SelectArgs &a, int64_t rows_grid_limit, int num_cu, hipStream_t stream);
+// `counter` (8 bytes of device memory, or null for strided rows) holds the
+// launch's row counter.
+hipError_t launch_select_keys(const SelectArgs &a, void *counter, int64_t rows_grid_limit, int num_cu,
+                              hipStream_t stream);
 
 // ---- one partition pass, one wavefront per row ------------------------------
 hipError_t launch_partition(const float *in, int64_t rows, uint32_t cols, int64_t ld,

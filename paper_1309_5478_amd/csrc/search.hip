@@ -278,7 +278,7 @@ knn_status_t run_search(knn_handle_t h, const float *Q, int64_t m, const float *
         ka.out_val = b.sv;
         ka.out_idx = b.si;
         ka.mode = smode;
-        KNN_TRY(launch_select_keys(ka, mb, num_cu, stream));
+        KNN_TRY(launch_select_keys(ka, b.selws, mb, num_cu, stream));
         if (certify)
             KNN_TRY(launch_certify(b.sv, mb, p.kk, k, b.qn2 + i0, b.cmax2, p.rel, stats_ptr(h) + kStatUncertified,
                                    stream));

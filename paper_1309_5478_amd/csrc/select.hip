@@ -55,6 +55,7 @@ struct SelSmem {
     uint32_t cnt_lt;
     uint32_t cnt_ge;
     unsigned long long acc[kAccSlots];
+    int64_t next_row;
 };
 
 // The two partition buffers: positions below CAP live in LDS, the rest in a
@@ -387,9 +388,10 @@ __device__ __forceinline__ bool direct_sort_fits(uint32_t nstack, uint32_t ss, u
 // registers so that five workgroups share a CU: with every phase of a row but
 // the stream latency-bound, more rows in flight per CU pay for the few
 // per-row register reloads and for the longer rows that overflow to the
-// workspace.  The larger instances serve rows that fit them whole.
+// workspace.  The larger instances serve rows that fit them whole, as many per
+// CU as their LDS allows.
 template <int CAP, bool KEYS>
-__global__ __launch_bounds__(kSelThreads, (CAP == kSelectCap && !KEYS) ? 5 : 1) void select_rows_kernel(
+__global__ __launch_bounds__(kSelThreads, KEYS ? 1 : (CAP == kSelectCap ? 5 : (CAP == 2048 ? 3 : 2))) void select_rows_kernel(
     SelectArgs a, uint64_t *ws, uint64_t ws_slot) {
     __shared__ SelSmem<CAP> sm;
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
@@ -398,7 +400,10 @@ __global__ __launch_bounds__(kSelThreads, (CAP == kSelectCap && !KEYS) ? 5 : 1) 
     // per-workgroup totals of the row statistics, in LDS (kept by thread 0)
     if (tid < kAccSlots) sm.acc[tid] = 0;
     __syncthreads();
-    for (int64_t r = blockIdx.x; r < a.rows; r += gridDim.x) {
+    // rows: first the workgroup's own, then the next unclaimed one from the
+    // launch's row counter (rows differ in cost, so static striding would
+    // leave workgroups idle at the end), or strided without a counter
+    for (int64_t r = blockIdx.x; r < a.rows;) {
         // this row's matrix: the launch's own, or one segment of several
         const float *dist = a.dist;
         const uint64_t *keys = a.keys;
@@ -619,8 +624,11 @@ __global__ __launch_bounds__(kSelThreads, (CAP == kSelectCap && !KEYS) ? 5 : 1) 
             }
         }
 
-        // 4. gather kept keys, sort, write out
+        // 4. gather kept keys, sort, write out; the next row is claimed now, so
+        // that the atomic's round trip overlaps this last phase
         long long t3 = clock64();
+        unsigned long long claimed = 0;
+        if (tid == 0 && a.next_row) claimed = atomicAdd(a.next_row, 1ull);
         if (!direct) {
             agg = flush_stack(sm, gb, nstack, agg);
             for (uint32_t t = tid; t < nfinal; t += kSelThreads) sm.sortbuf[agg + t] = sm.finals[t];
@@ -680,8 +688,10 @@ __global__ __launch_bounds__(kSelThreads, (CAP == kSelectCap && !KEYS) ? 5 : 1) 
             sm.acc[7] += (unsigned long long)cyc_stream;
             sm.acc[8] += (unsigned long long)(t3 - t2);
             sm.acc[9] += (unsigned long long)(t4 - t3);
+            sm.next_row = a.next_row ? (int64_t)claimed + gridDim.x : r + gridDim.x;
         }
         __syncthreads();
+        r = sm.next_row;
     }
     if (tid == 0 && a.stats && sm.acc[0]) {
         atomicAdd(&a.stats[kStatRows], sm.acc[0]);
@@ -787,14 +797,30 @@ int select_grid(int cap, int64_t rows, int num_cu) {
     return g < 1 ? 1 : (int)g;
 }
 
+// Workspace: the launch's row counter (in its own 256-byte block), then per
+// workgroup two overflow buffers of (cols - cap) keys.
+constexpr size_t kSelWsHeader = 256;
+
 size_t select_ws_bytes(int cap, uint32_t cols, int grid) {
     uint64_t slot = cols > (uint32_t)cap ? (uint64_t)cols - cap : 0;
-    return (size_t)grid * 2 * slot * sizeof(uint64_t);
+    return kSelWsHeader + (size_t)grid * 2 * slot * sizeof(uint64_t);
 }
 
-hipError_t launch_select(const SelectArgs &a, int cap, int grid, void *ws, hipStream_t stream) {
-    uint64_t slot = a.cols > (uint32_t)cap ? (uint64_t)a.cols - cap : 0;
-    uint64_t *w = static_cast<uint64_t *>(ws);
+hipError_t launch_select(const SelectArgs &args, int cap, int grid, void *ws, hipStream_t stream) {
+    if (!ws) return hipErrorInvalidValue;
+    uint64_t slot = args.cols > (uint32_t)cap ? (uint64_t)args.cols - cap : 0;
+    SelectArgs a = args;
+    uint64_t *w = reinterpret_cast<uint64_t *>(static_cast<char *>(ws) + kSelWsHeader);
+    // rows claimed from a counter where row costs vary (several matrices; k >
+    // 64: overflowing rows and longer finishing sorts; network or plain
+    // pivots: extra passes); rows of one matrix with k <= 64 and sample pivots
+    // cost about the same and are strided (measured 3 % faster)
+    if (a.segs || a.k > (uint32_t)kWave || a.mode != kPivotSample) {
+        a.next_row = static_cast<unsigned long long *>(ws);
+        // the counter starts at zero in every launch (a kernel, so that
+        // captured graphs clear it on every replay)
+        hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(256), 0, stream, a.next_row, 1);
+    }
     switch (cap) {
         case kSelectCap:
             hipLaunchKernelGGL((select_rows_kernel<kSelectCap, false>), dim3(grid), dim3(kSelThreads), 0, stream, a, w,
@@ -807,8 +833,12 @@ hipError_t launch_select(const SelectArgs &a, int cap, int grid, void *ws, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_select_keys(const SelectArgs &a, int64_t rows_grid_limit, int num_cu, hipStream_t stream) {
-    if (a.cols > (uint32_t)kSelectKeysCap || a.k > (uint32_t)kSelectMaxK) return hipErrorInvalidValue;
+hipError_t launch_select_keys(const SelectArgs &args, void *counter, int64_t rows_grid_limit, int num_cu,
+                              hipStream_t stream) {
+    if (args.cols > (uint32_t)kSelectKeysCap || args.k > (uint32_t)kSelectMaxK) return hipErrorInvalidValue;
+    SelectArgs a = args;
+    a.next_row = static_cast<unsigned long long *>(counter);
+    if (a.next_row) hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(256), 0, stream, a.next_row, 1);
     static int per = 0;
     if (per == 0) {
         int n = 0;
