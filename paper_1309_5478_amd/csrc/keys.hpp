@@ -22,6 +22,13 @@ __device__ __forceinline__ uint32_t ord32(float v) {
     return (v != v) ? kOrdNaN : o;
 }
 
+// ord32 of a value known not to be NaN.
+__device__ __forceinline__ uint32_t ord32_not_nan(float v) {
+    uint32_t u = __float_as_uint(v);
+    u = (v == 0.0f) ? 0u : u;
+    return u ^ ((uint32_t)((int32_t)u >> 31) | 0x80000000u);
+}
+
 // Inverse of ord32 for every class that has one representative (not for the
 // zero class, which returns +0, nor the NaN class).
 __device__ __forceinline__ float ord_to_float(uint32_t o) {
@@ -33,6 +40,12 @@ __device__ __forceinline__ float ord_to_float(uint32_t o) {
 // so keys are distinct and ties resolve to the lower index.
 __device__ __forceinline__ uint64_t make_key(float v, uint32_t idx) {
     return ((uint64_t)ord32(v) << 32) | idx;
+}
+// The same from an ordered value class, as a register pair (no 64-bit shift or add).
+__device__ __forceinline__ uint64_t key_of(uint32_t ord, uint32_t idx) {
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+    const u32x2 w = {idx, ord};
+    return __builtin_bit_cast(uint64_t, w);
 }
 __device__ __forceinline__ uint32_t key_idx(uint64_t k) { return (uint32_t)k; }
 __device__ __forceinline__ uint32_t key_ord(uint64_t k) { return (uint32_t)(k >> 32); }

@@ -110,11 +110,14 @@ constexpr uint32_t kTile4 = kSelThreads * kStreamU;   // float4s per tile
 // value: entries with v <= tv survive (the threshold key (ord(tv), ~0u) sits
 // above every key of that value).  One compare and one ballot per entry, one LDS
 // atomic per wave for the whole tile, then each non-empty ballot writes its
-// survivors at the running offset plus the lane's mbcnt slot.
+// survivors at the running offset plus the lane's mbcnt slot.  A survivor is
+// never NaN (the compare is false for NaN), so its key skips the NaN class, and
+// when the tile's slots all lie in LDS (the usual case) the writes skip the
+// per-entry workspace test.
 template <int CAP>
 __device__ __forceinline__ void vote_tile_le(SelSmem<CAP> &sm, const GBuf &gb, const f32x4 *x, uint32_t t,
                                              float tv) {
-    const uint32_t tid = threadIdx.x, lane = lane_id();
+    const uint32_t tid = threadIdx.x;
     uint64_t m[kStreamU * 4];
     uint32_t total = 0;
 #pragma unroll
@@ -128,16 +131,25 @@ __device__ __forceinline__ void vote_tile_le(SelSmem<CAP> &sm, const GBuf &gb, c
     for (uint32_t i = 0; i < kStreamU * 4; ++i) total += (uint32_t)__popcll(m[i]);
     if (total == 0) return;
     uint32_t base = 0;
-    if (lane == 0) base = atomicAdd(&sm.cnt_lt, total);
+    if (lane_id() == 0) base = atomicAdd(&sm.cnt_lt, total);
     base = wave_bcast0(base);
+    const bool in_lds = base + total <= (uint32_t)CAP;  // (uniform)
+    const uint32_t j0 = (t * kTile4 + tid) * 4;
 #pragma unroll
     for (uint32_t u = 0; u < kStreamU; ++u) {
-        const uint32_t j = (t * kTile4 + u * kSelThreads + tid) * 4;
 #pragma unroll
         for (uint32_t c = 0; c < 4; ++c) {
             const uint64_t mm = m[4 * u + c];
             if (mm) {
-                if ((mm >> lane) & 1ull) vst(sm, gb, 0, base + lanes_below(mm), make_key(x[u][c], j + c));
+                const float v = x[u][c];
+                if (v <= tv) {  // this lane's own vote
+                    const uint32_t slot = base + lanes_below(mm);
+                    const uint64_t key = key_of(ord32_not_nan(v), j0 + (u * kSelThreads * 4 + c));
+                    if (in_lds)
+                        sm.buf[0][slot] = key;
+                    else
+                        vst(sm, gb, 0, slot, key);
+                }
                 base += (uint32_t)__popcll(mm);
             }
         }
