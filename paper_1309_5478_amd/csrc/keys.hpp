@@ -89,17 +89,19 @@ __device__ __forceinline__ bool key_below(float v, uint32_t j, const Pivot &p) {
 
 // The value of lane (lane ^ mask), every lane of the wave active.  Masks 1, 2
 // and 8 are single DPP moves (quad permutations, a rotation by 8 within rows
-// of 16), mask 4 two row shifts and a select, mask 16 a swizzle within halves
-// of 32; only mask 32 and others go through the LDS crossbar.
+// of 16), mask 4 two DPP moves (half-row mirror, quad reversal), mask 16 a
+// swizzle within halves of 32; only mask 32 and others go through the LDS
+// crossbar.
 __device__ __forceinline__ uint32_t xor_lanes32(uint32_t v, int mask) {
     const int x = (int)v;
     switch (mask) {
         case 1: return (uint32_t)__builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false);  // quad_perm 1,0,3,2
         case 2: return (uint32_t)__builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, false);  // quad_perm 2,3,0,1
         case 4: {
-            const int up = __builtin_amdgcn_mov_dpp(x, 0x104, 0xF, 0xF, false);  // row_shl:4, lane + 4
-            const int dn = __builtin_amdgcn_mov_dpp(x, 0x114, 0xF, 0xF, false);  // row_shr:4, lane - 4
-            return (uint32_t)((lane_id() & 4) ? dn : up);
+            // lane ^ 7 within groups of 8 (row_half_mirror), then lane ^ 3
+            // within quads: (i ^ 7) ^ 3 = i ^ 4
+            const int m = __builtin_amdgcn_mov_dpp(x, 0x141, 0xF, 0xF, false);  // row_half_mirror
+            return (uint32_t)__builtin_amdgcn_mov_dpp(m, 0x1B, 0xF, 0xF, false);  // quad_perm 3,2,1,0
         }
         case 8: return (uint32_t)__builtin_amdgcn_mov_dpp(x, 0x128, 0xF, 0xF, false);  // row_ror:8
         case 16: return (uint32_t)__builtin_amdgcn_ds_swizzle(x, 0x401F);                    // xor 16 in 32
