@@ -81,6 +81,24 @@ __device__ __forceinline__ void vst(SelSmem<CAP> &sm, const GBuf &gb, uint32_t b
     else __hip_atomic_store(gb.at(b) + (p - CAP), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// While a row is streamed, buffer 0 extends through both LDS buffers: positions
+// below 2 CAP are LDS (buffer 1 holding [CAP, 2 CAP)), the rest sit in the
+// workspace where buffer 0 keeps them (g0[p - CAP]).  normalize_first moves
+// [CAP, 2 CAP) of a streamed range to the workspace, restoring buffer 0's own
+// layout before anything else uses the buffers.
+template <int CAP>
+__device__ __forceinline__ void vst_first(SelSmem<CAP> &sm, const GBuf &gb, uint32_t p, uint64_t v) {
+    if (p < 2u * CAP) (&sm.buf[0][0])[p] = v;
+    else __hip_atomic_store(gb.g0 + (p - CAP), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+template <int CAP>
+__device__ __forceinline__ void normalize_first(SelSmem<CAP> &sm, const GBuf &gb, uint32_t lo, uint32_t hi) {
+    const uint32_t a = lo > (uint32_t)CAP ? lo : (uint32_t)CAP, b = hi < 2u * CAP ? hi : 2u * CAP;
+    for (uint32_t p = a + threadIdx.x; p < b; p += kSelThreads)
+        __hip_atomic_store(gb.g0 + (p - CAP), sm.buf[1][p - CAP], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __syncthreads();
+}
+
 // Wave-level append of the lanes set in `m` into buffer 0 at the running counter.
 template <int CAP>
 __device__ __forceinline__ void wave_append(SelSmem<CAP> &sm, const GBuf &gb, uint64_t m, bool mine, float v,
@@ -89,7 +107,7 @@ __device__ __forceinline__ void wave_append(SelSmem<CAP> &sm, const GBuf &gb, ui
     uint32_t base = 0;
     if (lane == 0) base = atomicAdd(&sm.cnt_lt, (uint32_t)__popcll(m));
     base = wave_bcast0(base);
-    if (mine) vst(sm, gb, 0, base + lanes_below(m), make_key(v, j));
+    if (mine) vst_first(sm, gb, base + lanes_below(m), make_key(v, j));
 }
 
 // Generic vote of one entry per lane: key in [LO, P) (BAND) or below P, then
@@ -110,10 +128,10 @@ constexpr uint32_t kTile4 = kSelThreads * kStreamU;   // float4s per tile
 // value: entries with v <= tv survive (the threshold key (ord(tv), ~0u) sits
 // above every key of that value).  One compare and one ballot per entry, one LDS
 // atomic per wave for the whole tile, then each non-empty ballot writes its
-// survivors at the running offset plus the lane's mbcnt slot.  A survivor is
-// never NaN (the compare is false for NaN), so its key skips the NaN class, and
-// when the tile's slots all lie in LDS (the usual case) the writes skip the
-// per-entry workspace test.
+// survivors at the running offset plus the lane's mbcnt slot (streaming layout
+// of buffer 0).  A survivor is never NaN (the compare is false for NaN), so its
+// key skips the NaN class, and when the tile's slots all lie in LDS (the usual
+// case) the writes skip the per-entry workspace test.
 template <int CAP>
 __device__ __forceinline__ void vote_tile_le(SelSmem<CAP> &sm, const GBuf &gb, const f32x4 *x, uint32_t t,
                                              float tv) {
@@ -133,7 +151,7 @@ __device__ __forceinline__ void vote_tile_le(SelSmem<CAP> &sm, const GBuf &gb, c
     uint32_t base = 0;
     if (lane_id() == 0) base = atomicAdd(&sm.cnt_lt, total);
     base = wave_bcast0(base);
-    const bool in_lds = base + total <= (uint32_t)CAP;  // (uniform)
+    const bool in_lds = base + total <= 2u * CAP;  // (uniform)
     const uint32_t j0 = (t * kTile4 + tid) * 4;
 #pragma unroll
     for (uint32_t u = 0; u < kStreamU; ++u) {
@@ -146,9 +164,9 @@ __device__ __forceinline__ void vote_tile_le(SelSmem<CAP> &sm, const GBuf &gb, c
                     const uint32_t slot = base + lanes_below(mm);
                     const uint64_t key = key_of(ord32_not_nan(v), j0 + (u * kSelThreads * 4 + c));
                     if (in_lds)
-                        sm.buf[0][slot] = key;
+                        (&sm.buf[0][0])[slot] = key;
                     else
-                        vst(sm, gb, 0, slot, key);
+                        vst_first(sm, gb, slot, key);
                 }
                 base += (uint32_t)__popcll(mm);
             }
@@ -439,6 +457,7 @@ __global__ __launch_bounds__(kSelThreads, KEYS ? 1 : (CAP == kSelectCap ? 5 : (C
         const float *row = dist + lr * ld;
         const bool vec = ((reinterpret_cast<uintptr_t>(dist) & 15u) == 0) && ((ld & 3) == 0);
         uint32_t nstack = 0, agg = 0, passes = 0, stream_passes = 0, spill = 0, first = 0;
+        uint32_t wide_lo = 0, wide_hi = 0;  // streamed range of buffer 0 still in the streaming layout
         long long cyc_sample = 0, cyc_stream = 0;
         uint32_t sb, ss, se, Kp;  // active segment (buffer, start, end) and keys still needed
 
@@ -545,12 +564,16 @@ __global__ __launch_bounds__(kSelThreads, KEYS ? 1 : (CAP == kSelectCap ? 5 : (C
                 uint32_t L = total - base;
                 ++stream_passes;
                 if (stream_passes == 1) first = L;
-                if (total > (uint32_t)CAP) spill = 1;
+                if (total > 2u * CAP) spill = 1;
+                wide_lo = base;
+                wide_hi = total;
                 if (L >= Kp) {
                     sb = 0; ss = base; se = total;
                     break;
                 }
                 // too few below the pivot: keep them all, move the band up
+                if (wide_hi > (uint32_t)CAP) normalize_first(sm, gb, wide_lo, wide_hi);
+                wide_hi = 0;
                 push_seg(sm, gb, 0, base, total, nstack, agg, false);
                 Kp -= L;
                 base = total;
@@ -588,12 +611,14 @@ __global__ __launch_bounds__(kSelThreads, KEYS ? 1 : (CAP == kSelectCap ? 5 : (C
         bool direct = false;
         for (;;) {
             uint32_t len = se - ss;
-            if (Kp == len) {
-                push_seg(sm, gb, sb, ss, se, nstack, agg, true);
-                break;
-            }
             if (direct_sort_fits<CAP>(nstack, ss, se, Kp, k)) {
                 direct = true;
+                break;
+            }
+            if (wide_hi > (uint32_t)CAP) normalize_first(sm, gb, wide_lo, wide_hi);
+            wide_hi = 0;
+            if (Kp == len) {
+                push_seg(sm, gb, sb, ss, se, nstack, agg, true);
                 break;
             }
             if (passes >= (uint32_t)kMaxPasses) {
@@ -667,15 +692,22 @@ __global__ __launch_bounds__(kSelThreads, KEYS ? 1 : (CAP == kSelectCap ? 5 : (C
             // buffers together are the sort's exchange area
             uint64_t *xb = &sm.buf[0][0];
             const uint32_t len = se;
-            auto load = [&](uint32_t p) { return p < len ? vld(sm, gb, sb, p) : kKeyMax; };
-            if (len <= (uint32_t)kSelThreads)
-                block_sort_regs_from<kSelThreads, 1, true>(xb, load);
-            else if (len <= 2u * kSelThreads)
-                block_sort_regs_from<kSelThreads, 2, true>(xb, load);
-            else if (len <= 4u * kSelThreads)
-                block_sort_regs_from<kSelThreads, 4, true>(xb, load);
-            else
-                block_sort_regs_from<kSelThreads, 8, true>(xb, load);
+            if (wide_hi > (uint32_t)CAP) {
+                // still in the streaming layout (sb == 0): more than CAP and at
+                // most 2 CAP keys, wholly in LDS, sorted in place
+                auto load = [&](uint32_t p) { return p < len ? xb[p] : kKeyMax; };
+                block_sort_regs_from<kSelThreads, 8, false>(xb, load);
+            } else {
+                auto load = [&](uint32_t p) { return p < len ? vld(sm, gb, sb, p) : kKeyMax; };
+                if (len <= (uint32_t)kSelThreads)
+                    block_sort_regs_from<kSelThreads, 1, true>(xb, load);
+                else if (len <= 2u * kSelThreads)
+                    block_sort_regs_from<kSelThreads, 2, true>(xb, load);
+                else if (len <= 4u * kSelThreads)
+                    block_sort_regs_from<kSelThreads, 4, true>(xb, load);
+                else
+                    block_sort_regs_from<kSelThreads, 8, true>(xb, load);
+            }
             for (uint32_t t = tid; t < k; t += kSelThreads) emit(t, xb[t]);
         } else if (k <= (uint32_t)kWave) {
             if (wave == 0) {
