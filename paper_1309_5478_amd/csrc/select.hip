@@ -1,9 +1,10 @@
 // Quick multi-select over the rows of a given FP32 distance matrix (Methods,
 // "GPU-based quick multi-select").
 //
-// Coarse level: rows are independent; a persistent grid of workgroups strides
-// over them (one workgroup per row at a time, the paper's block-per-query
-// variant, with 256-lane workgroups of four 64-lane waves).
+// Coarse level: rows are independent; a persistent grid of workgroups takes
+// them one at a time (strided, or claimed from a row counter where row costs
+// vary; the paper's block-per-query variant, with 256-lane workgroups of four
+// 64-lane waves).
 //
 // Fine level, per row:
 //  1. A pivot is chosen from a strided sample of the row (16 blocks of 64
@@ -14,20 +15,22 @@
 //     "key below pivot" with a 64-lane ballot; a lane's slot is the population
 //     count of the set lanes below it (mbcnt), the wave reserves its slots with
 //     one LDS atomic on the running counter (the paper's g< counter), and the
-//     survivors are written to an on-chip buffer.  Keys at or above the pivot
-//     are not needed while L >= K (the paper's K < L case: only the left side is
-//     processed) and are not stored.  If L < K the left side is kept (pushed as
-//     a segment reference) and the row is streamed again for the band between
-//     the old pivot and a higher one.
+//     survivors are written on chip (both buffers while streaming).  Keys at
+//     or above the pivot are not needed while L >= K (the paper's K < L case:
+//     only the left side is processed) and are not stored.  If L < K the left
+//     side is kept (pushed as a segment reference) and the row is streamed
+//     again for the band between the old pivot and a higher one.
 //  3. Quickselect passes over the survivors, each a two-sided partition from one
 //     buffer into the other at the same positions (keys below the pivot from the
 //     left end, the others from the right end), K-versus-L recursion, and a stack
-//     of segment references to kept left sides instead of copying them.
-//  4. The kept keys are gathered, bitonic-sorted in LDS and written out.
+//     of segment references to kept left sides instead of copying them -- until
+//     a segment with nothing set aside is short enough to be sorted whole.
+//  4. The kept keys are gathered, bitonic-sorted in registers and LDS and
+//     written out (or the short segment is sorted and its first k written).
 //
 // Keys are (ordered value, column index), so every key is distinct, every pass
 // makes progress and equal values resolve to the lower index.  The on-chip
-// buffers hold CAP keys; positions at or above CAP live in a per-workgroup
+// buffers hold CAP keys each; positions beyond them live in a per-workgroup
 // global workspace, so overflowing rows stay exact.
 #include "internal.hpp"
 #include "keys.hpp"
