@@ -67,6 +67,20 @@ def test_select_random_sizes(h, torch, cols, pivot):
         check_select(h, torch, D, k, pivot, tag="random")
 
 
+@pytest.mark.parametrize("cols", [1025, 2047, 2048, 2049, 2300, 4100])
+def test_select_around_two_buffers(h, torch, cols):
+    """Rows whose survivors straddle one LDS buffer (1024 keys), both buffers
+    (2048) and the workspace beyond, at k where the finish sorts the streamed
+    run in place (k >= 512), sorts it after it moved (k < 512) or runs the
+    partition passes; sample and network pivots, plus adversarial rows."""
+    rng = np.random.default_rng(cols + 17)
+    D = np.concatenate([rng.standard_normal((24, cols)).astype(np.float32),
+                        np.stack(list(synth.adversarial_rows(cols, seed=cols).values()))])
+    for k in sorted({300, 511, 512, 700, 1000, 1024} & set(range(1, min(cols, 1024) + 1))):
+        for pivot in ("sample", "learned"):
+            check_select(h, torch, D, k, pivot, tag="two-buffer")
+
+
 @pytest.mark.parametrize("cols", [3000, 70001])
 @pytest.mark.parametrize("pivot", PIVOTS)
 def test_select_adversarial_rows(h, torch, cols, pivot):
