@@ -10,6 +10,11 @@ before the timed region.  Also reported: quick multi-select throughput on a
 materialised 8192 x 262144 block of the same graph's squared-distance matrix
 (k = 32), per pivot rule, and the CPU oracle timed on a bounded row sample.
 
+With --workload lowprec the step is one knn_graph on N = 2^20 points, d = 256,
+k = 64 (Gaussian mixture) with the distance product in BF16, 4x oversampled
+candidates and the exact FP32 re-rank; FP8 and FP32 products are timed once
+beside it, with recall against the FP64 oracle on 32 sampled rows.
+
 With --workload batch the step is instead one knn_batch_search over 512
 uneven jobs (corpus sizes log-uniform in [1e3, 1e6], 1024 queries each, d in
 {64, 128, 768}, k log-uniform in [1, 1024], uniform or Gaussian-mixture data
@@ -29,6 +34,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_MFMA_TFLOPS = 157.3   # MI355X dense FP32 matrix peak
+PEAK_MFMA_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}  # dense matrix peaks
 PEAK_HBM_GBS = 8000.0           # MI355X HBM3E peak
 METRIC = "k-NNG rows/s & select GB/s (N=262144,d=1024,k=32), learned vs plain pivots"
 
@@ -67,7 +73,7 @@ def main():
     ap.add_argument("--no-select", action="store_true", help="skip the select_k block")
     ap.add_argument("--no-pivot-compare", action="store_true", help="skip the per-pivot-rule steps")
     ap.add_argument("--cpu-rows", type=int, default=1536, help="query rows in the CPU oracle sample (0: skip)")
-    ap.add_argument("--workload", default="knng", choices=["knng", "batch", "select"])
+    ap.add_argument("--workload", default="knng", choices=["knng", "batch", "select", "lowprec"])
     ap.add_argument("--batch-jobs", type=int, default=512)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference dispatch for memory counters)")
@@ -90,6 +96,8 @@ def main():
         return bench_batch(args, knn, torch, np)
     if args.workload == "select":
         return bench_select(args, knn, torch, np)
+    if args.workload == "lowprec":
+        return bench_lowprec(args, knn, torch, np, synth)
     N, d, k = args.n, args.d, args.k
     t0 = time.perf_counter()
     P = synth.gmm_points(N, d, seed=synth.SEEDS["knng_fused"])
@@ -274,6 +282,81 @@ def bench_select(args, knn, torch, np):
         "roofline": {"bound": "hbm", "kernel": "select_rows_kernel", "achieved": round(gbs, 1),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None},
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_lowprec(args, knn, torch, np, synth):
+    N, d, k = 1 << 20, 256, 64
+    t0 = time.perf_counter()
+    P = synth.gmm_points(N, d, seed=synth.SEEDS["lowprec"])
+    log(f"generated {N}x{d} points in {time.perf_counter() - t0:.1f} s")
+    dev = torch.from_numpy(P).cuda()
+    torch.cuda.synchronize()
+    h = knn.Handle(0)
+    rows = np.random.default_rng(0).choice(N, 32, replace=False)
+    import oracle
+    threads = oracle.default_threads()
+    a = time.perf_counter()
+    od, oi = oracle.knn(P[rows], P, k, self_ids=rows, nthreads=threads)
+    cpu_sec = time.perf_counter() - a
+
+    def run(prec, steps, warmup):
+        for _ in range(warmup):
+            h.graph(dev, k, precision=prec, flags=knn.FLAG_TIMING)
+            h.stats()
+        torch.cuda.synchronize()
+        tot = {"product_ms": 0.0, "product_flops": 0.0, "product_launches": 0, "fallback_rows": 0}
+        t = time.perf_counter()
+        for _ in range(steps):
+            gd, gi = h.graph(dev, k, precision=prec, flags=knn.FLAG_TIMING)
+            st = h.stats()   # synchronises the stream
+            for key in tot:
+                tot[key] += st[key]
+        sec = (time.perf_counter() - t) / steps
+        g = gi.cpu().numpy()[rows]
+        gdist = gd.cpu().numpy()[rows].astype(np.float64)
+        recall = sum(len(set(x.tolist()) & set(y.tolist())) for x, y in zip(g, oi)) / (len(rows) * k)
+        rel = float(np.max(np.abs(gdist - od) / np.maximum(np.abs(od), 1e-30)))
+        tf = tot["product_flops"] / (tot["product_ms"] / 1e3) / 1e12 if tot["product_ms"] > 0 else 0.0
+        r = {"ms_per_step": round(sec * 1e3, 2), "rows_per_s": round(N / sec, 1),
+             "product_ms_per_launch": round(tot["product_ms"] / max(tot["product_launches"], 1), 3),
+             "product_tflops": round(tf, 1), "frac_of_peak": round(tf / PEAK_MFMA_TFLOPS[prec], 4),
+             "fallback_rows_per_step": tot["fallback_rows"] / steps, "recall": recall, "max_rel_dist_err": rel}
+        log(f"knn_graph {prec}: {r['ms_per_step']} ms/step, {r['rows_per_s']:.0f} rows/s; product {tf:.1f} TFLOP/s"
+            f" ({100 * r['frac_of_peak']:.1f} % of peak), recall {recall}, max rel. distance error {rel:.2e}")
+        return r, tot
+
+    res, tot = run("bf16", args.steps, args.warmup)
+    others = {p: run(p, 1, 1)[0] for p in ("fp8", "fp32")}
+    achieved = res["product_tflops"]
+    line = {
+        "metric": "reduced-precision k-NNG rows/s (N=2^20, d=256, k=64, BF16 product + FP32 re-rank)",
+        "value": res["rows_per_s"],
+        "unit": "rows/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": f"reduced-precision k-NNG, N={N}, d={d}, k={k}, Gaussian mixture (64 comp.),"
+                               " BF16 product, k' = 4k candidates, exact FP32 re-rank",
+                   "N": N, "d": d, "k": k, "oversample": 4},
+        "bf16": res,
+        "fp8": others["fp8"],
+        "fp32": others["fp32"],
+        "roofline": {"bound": "mfma", "kernel": "dist_gemm_kernel (fused filter epilogue, BF16)",
+                     "achieved": achieved, "peak": PEAK_MFMA_TFLOPS["bf16"], "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_MFMA_TFLOPS["bf16"], 4), "traffic": None,
+                     "launch_ms": res["product_ms_per_launch"],
+                     "flops_per_launch": tot["product_flops"] / max(tot["product_launches"], 1)},
+        "cpu_baseline": {"value": round(len(rows) / cpu_sec, 3), "unit": "rows/s", "cores": threads, "kind": "oracle",
+                         "sample": f"{len(rows)} query rows (FP64 direct distances to all {N} points + stable sort),"
+                                   f" {cpu_sec:.1f} s"},
     }
     print(json.dumps(line), flush=True)
 
