@@ -60,6 +60,36 @@ def measured_traffic():
     return value if have == want else None
 
 
+def parity_block(Q, C, rows, gd, gi, od, oi, k, self_ids=None, band=1e-5, tol=1e-5):
+    """GPU rows (gd, gi: the listed query rows, k columns) against the oracle's
+    k + 1 nearest (od, oi; FP64 direct distances, stable order).  A row whose set
+    differs only by points within the near-tie band of the oracle's k-th
+    distance counts as a near tie; any other difference is a mismatch.  Every
+    returned distance is compared with its FP64 direct value."""
+    import numpy as np
+    mismatch = near = bad_dist = 0
+    max_rel = 0.0
+    for t, r in enumerate(rows):
+        g = gi[t].astype(np.int64)
+        diff = Q[r].astype(np.float64)[None, :] - C[g].astype(np.float64)
+        ref = np.einsum("ij,ij->i", diff, diff)
+        nz = ref > 0
+        rel = np.abs(gd[t].astype(np.float64) - ref)
+        if nz.any():
+            max_rel = max(max_rel, float(np.max(rel[nz] / ref[nz])))
+        bad_dist += int(np.sum(rel[nz] > tol * ref[nz]))
+        gs, os_ = set(g.tolist()), set(oi[t, :k].tolist())
+        ok = len(gs) == k and (self_ids is None or int(self_ids[t]) not in gs)
+        if ok and gs != os_:
+            kth = od[t, k - 1]
+            ok = all(abs(float(np.dot(Q[r].astype(np.float64) - C[j], Q[r].astype(np.float64) - C[j])) - kth)
+                     <= band * max(kth, 1e-30) for j in gs ^ os_)
+            near += int(ok)
+        mismatch += int(not ok)
+    return {"rows": int(len(rows)), "set_mismatch": int(mismatch), "near_ties": int(near),
+            "dist_errors": int(bad_dist), "max_rel_dist_err": max_rel, "tolerance": tol}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,15 +143,17 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    out = {}
+
     def step(pivot):
-        h.graph(dev, k, pivot=pivot, flags=flags)
+        out["d"], out["i"] = h.graph(dev, k, pivot=pivot, flags=flags)
         return h.stats()   # synchronises the stream
 
     for _ in range(args.warmup):
         step(args.pivot)
     torch.cuda.synchronize()
     prod_ms = prod_flops = 0.0
-    prod_launches = fallback = cands = 0
+    prod_launches = fallback = cands = uncert = 0
     t0 = time.perf_counter()
     for _ in range(args.steps):
         st = step(args.pivot)
@@ -130,8 +162,10 @@ def main():
         prod_launches += st["product_launches"]
         fallback += st["fallback_rows"]
         cands += st["candidates_total"]
+        uncert += st["rows_uncertified"]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    g_dist, g_idx = out["d"].cpu().numpy(), out["i"].cpu().numpy()   # the last timed step's output
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     rows_per_s = N / (ms_per_step / 1e3)
     achieved = prod_flops / (prod_ms / 1e3) / 1e12 if prod_ms > 0 else 0.0
@@ -174,18 +208,22 @@ def main():
         del D
         torch.cuda.empty_cache()
 
-    cpu = None
+    cpu = parity = None
     if args.cpu_rows > 0:
         import oracle
-        rows = np.random.default_rng(0).choice(N, args.cpu_rows, replace=False)
+        rows = np.sort(np.random.default_rng(0).choice(N, args.cpu_rows, replace=False))
         threads = oracle.default_threads()
         a = time.perf_counter()
-        oracle.knn(P[rows], P, k, self_ids=rows, nthreads=threads)
+        od, oi = oracle.knn(P[rows], P, k + 1, self_ids=rows, nthreads=threads)
         sec = time.perf_counter() - a
         cpu = {"value": round(args.cpu_rows / sec, 3), "unit": "rows/s", "cores": threads, "kind": "oracle",
                "sample": f"{args.cpu_rows} query rows of the same k-NNG (FP64 direct distances to all {N} points"
                          f" + stable sort), {sec:.1f} s"}
         log(f"oracle: {cpu['value']} rows/s on {threads} threads")
+        # the same rows of the last timed GPU step against the oracle
+        parity = parity_block(P, P, rows, g_dist[rows], g_idx[rows], od, oi, k, self_ids=rows)
+        parity["rows_uncertified"] = uncert // max(args.steps, 1)
+        log(f"parity: {parity}")
 
     line = {
         "metric": METRIC,
@@ -212,9 +250,13 @@ def main():
         "select": select,
         "fallback_rows_per_step": fallback / args.steps,
         "candidates_per_row": round(cands / args.steps / N, 1),
+        "parity": parity,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+    if parity and (parity["set_mismatch"] or parity["dist_errors"]):
+        log("PARITY FAILURE: GPU rows differ from the oracle beyond the near-tie band / distance tolerance")
+        sys.exit(1)
 
 
 def bench_select(args, knn, torch, np):

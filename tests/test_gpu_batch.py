@@ -236,7 +236,7 @@ def test_batch_full_workload(h, knn, torch):
     """The full batched workload as the benchmark runs it (512 jobs, about
     100 GB of corpora drawn on the device, learned pivots, autotuned tiles,
     graph replay): every job's output equals its own knn_search call bit for
-    bit, and sampled rows of 16 jobs agree with the FP64 oracle."""
+    bit, and 16 sampled rows of each of 32 jobs agree with the FP64 oracle."""
     import oracle
     from synth.gpu import batch_jobs, job_points
     J = batch_jobs()
@@ -257,13 +257,13 @@ def test_batch_full_workload(h, knn, torch):
             assert bool(torch.all(gi[:, kc:] == -1)), f"job {t} padding"
     say("per-job parity done; oracle rows")
     rng = np.random.default_rng(11)
-    for t in rng.choice(len(J), 16, replace=False):
+    for t in rng.choice(len(J), 32, replace=False):
         q, c = data[t]
-        rows = np.sort(rng.choice(J[t]["m"], 4, replace=False))
+        rows = np.sort(rng.choice(J[t]["m"], 16, replace=False))
         kc = min(J[t]["k"], J[t]["n"])
         Qh = q.cpu().numpy()
         Ch = c.cpu().numpy()
         gd, gi = got[t][0].cpu().numpy(), got[t][1].cpu().numpy()
         near = compare(Qh, Ch, kc, gd[rows, :kc], gi[rows, :kc], rows)
-        say(f"job {t} (n={J[t]['n']}, d={J[t]['d']}, k={J[t]['k']}): 4 rows vs oracle, near ties {near}")
+        say(f"job {t} (n={J[t]['n']}, d={J[t]['d']}, k={J[t]['k']}): 16 rows vs oracle, near ties {near}")
         del Qh, Ch
