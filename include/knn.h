@@ -100,6 +100,9 @@ typedef struct {
  * handle, and in the JSON file named by KNN_AUTOTUNE_CACHE when that is set).
  * Also enabled by the environment variable KNN_AUTOTUNE=1. */
 #define KNN_FLAG_AUTOTUNE 0x10
+/* search / graph / batch with FP32 products: treat every row as uncertified, so
+ * that each row is re-run exactly from its materialised reduced-key row (tests). */
+#define KNN_FLAG_FORCE_RERUN 0x20
 
 typedef struct {
     int64_t rows;                 /* rows processed by the last call              */
@@ -119,6 +122,10 @@ typedef struct {
                                   /* (2 * rows * cols * d each)                    */
     int64_t rows_uncertified;     /* search / graph rows whose candidate margin    */
                                   /* does not exceed twice the key error bound     */
+    int64_t rows_rerun;           /* FP32 rows among them re-run exactly: every    */
+                                  /* point whose reduced key is within the bound   */
+                                  /* of the k-th candidate re-ranked by its exact  */
+                                  /* distance                                      */
 } knn_stats_t;
 
 /* Create a handle bound to HIP device `device` (must be gfx950). */
@@ -272,6 +279,29 @@ knn_status_t knn_distances(knn_handle_t h, const float *queries, int64_t m, cons
                            int64_t n, int32_t d, float *out, int64_t ldo, void *stream);
 
 /*
+ * knn_quantize -- the reduced-precision operands that knn_search / knn_graph
+ * feed to the matrix cores for KNN_PREC_BF16 and KNN_PREC_FP8_E4M3 (the paper
+ * computes in FP32; lower operand precision is this library's addition, with
+ * every candidate re-ranked in FP32).  Exported so that the conversion can be
+ * checked element by element.
+ *   X      n x d FP32 points                                      [in, device]
+ *   prec   KNN_PREC_BF16: BF16 codes (uint16), round to nearest even; a NaN
+ *          stays a quiet NaN with its sign.
+ *          KNN_PREC_FP8_E4M3: OCP e4m3 codes (uint8) of x * 2^e, where e is per
+ *          point the largest integer with amax 2^e <= 448 (amax: the largest
+ *          finite magnitude of the point; e = 0 without a finite non-zero
+ *          element; e limited to [-100, 100]); round to nearest even,
+ *          saturating at +-448 (infinities too); a NaN becomes the NaN code
+ *          S.1111.111.
+ *   out    n rows of ldo codes, ldo = d rounded up to a multiple of 128; the
+ *          padding codes are zero                                  [out, device]
+ *   scale  n FP32 scales 2^-e (FP8; NULL allowed for BF16)         [out, device]
+ * Errors: INVALID_VALUE for null pointers, n < 0, d < 1 or another precision.
+ */
+knn_status_t knn_quantize(knn_handle_t h, const float *X, int64_t n, int32_t d, int32_t prec, void *out,
+                          float *scale, void *stream);
+
+/*
  * Pivot network (learned first pivot of the quick multi-select).
  *
  * The paper leaves the pivot rule of its method open (Methods, "GPU-based quick
@@ -327,6 +357,43 @@ knn_status_t knn_pivot_grad(knn_handle_t h, const float *feats, const float *tar
  * be NULL. */
 knn_status_t knn_pivot_train_step(knn_handle_t h, const float *feats, const float *targets,
                                   int64_t B, float quantile, float lr, float *loss, void *stream);
+
+/*
+ * Training the pivot network on rows the method itself generates.
+ *
+ * knn_pivot_add_examples appends one training example per row of a distance
+ * matrix: the row's 8 features for `k` and the target y = (v_k - m) / s, the
+ * row's exact k-th smallest value (by knn_select_k) standardised with the
+ * sample location m and scale s the features use.  Rows whose features or
+ * target are not finite are skipped; the kept rows are appended in row order.
+ * The examples live on the device, owned by the handle, until
+ * knn_pivot_clear_examples.  Synchronous (returns once they are stored).
+ *   dist   rows x cols FP32, row stride ld, cols >= 256             [in, device]
+ *   k      1 <= k <= min(cols, 1024)
+ * Errors: INVALID_VALUE for bad sizes or a null pointer; UNSUPPORTED for
+ * cols < 256, cols > INT32_MAX or k > 1024; OUT_OF_MEMORY.
+ *
+ * knn_pivot_train trains the network from scratch on the stored examples and,
+ * when out_path is not NULL, writes it with knn_pivot_save.  Every step runs on
+ * the device: weights drawn from `seed` (He initialisation: normal weights of
+ * variance 2 / fan-in for the hidden layers and 1 / 64 for the output, zero
+ * biases, the output bias at the lower median of a strided sample of at most
+ * 2048 targets), then `steps` Adam steps (beta 0.9 / 0.999, eps 1e-8) on
+ * batches of min(4096, examples) drawn uniformly with replacement by a
+ * counter-based generator of (seed, step), pinball loss at quantile 0.99,
+ * learning rate 2e-3 decaying exponentially to 2e-4.  The result depends only
+ * on the examples, the seed and the step count.  Synchronous.
+ * Errors: INVALID_VALUE without examples or with steps < 0; IO if the file
+ * cannot be written.
+ */
+knn_status_t knn_pivot_add_examples(knn_handle_t h, const float *dist, int64_t rows, int64_t cols, int64_t ld,
+                                    int32_t k, void *stream);
+knn_status_t knn_pivot_clear_examples(knn_handle_t h);
+knn_status_t knn_pivot_example_count(knn_handle_t h, int64_t *count);
+/* Copies the stored examples (count x 8 features, count targets) into device
+ * arrays of at least max_rows rows.  Synchronous. */
+knn_status_t knn_pivot_get_examples(knn_handle_t h, float *feats, float *targets, int64_t max_rows);
+knn_status_t knn_pivot_train(knn_handle_t h, const char *out_path, uint64_t seed, int32_t steps);
 
 /* Counters of the last select / search / graph call on `h`.  Synchronises the
  * stream that call used. */

@@ -11,7 +11,7 @@ import ctypes
 
 from . import _abi
 from ._abi import (PIVOT_LEARNED, PIVOT_PLAIN, PIVOT_SAMPLE, PREC_BF16, PREC_FP32,  # noqa: F401
-                   PREC_FP8_E4M3, FLAG_FORCE_FALLBACK, FLAG_UNFUSED, FLAG_TIMING, FLAG_NO_GRAPH, FLAG_AUTOTUNE, Job, Options,
+                   PREC_FP8_E4M3, FLAG_FORCE_FALLBACK, FLAG_UNFUSED, FLAG_TIMING, FLAG_NO_GRAPH, FLAG_AUTOTUNE, FLAG_FORCE_RERUN, Job, Options,
                    Stats)
 
 _PIVOTS = {"plain": PIVOT_PLAIN, "sample": PIVOT_SAMPLE, "learned": PIVOT_LEARNED}
@@ -179,6 +179,24 @@ class Handle:
                                            ctypes.c_void_p(out.data_ptr()), n, self._stream()))
         return out
 
+    def quantize(self, x, precision):
+        """Reduced-precision operand codes of the rows of a contiguous FP32
+        device tensor: (codes [n, ldo] uint8 (FP8) or int16 (BF16 bits), ldo = d
+        rounded up to 128, scales [n] f32 or None)."""
+        torch = _torch()
+        if x.dim() != 2 or x.dtype != torch.float32 or not x.is_cuda or not x.is_contiguous():
+            raise ValueError("x must be a contiguous 2-D float32 device tensor")
+        n, d = x.shape
+        prec = _PRECS[precision] if isinstance(precision, str) else int(precision)
+        ldo = (d + 127) // 128 * 128
+        codes = torch.empty((n, ldo), dtype=torch.int16 if prec == PREC_BF16 else torch.uint8, device=x.device)
+        scale = torch.empty((n,), dtype=torch.float32, device=x.device) if prec == PREC_FP8_E4M3 else None
+        self._check(self.lib.knn_quantize(self.h, ctypes.c_void_p(x.data_ptr()), n, d, prec,
+                                          ctypes.c_void_p(codes.data_ptr()),
+                                          ctypes.c_void_p(scale.data_ptr() if scale is not None else 0),
+                                          self._stream()))
+        return codes, scale
+
     # ---- pivot network -------------------------------------------------------
     def pivot_set_weights(self, params):
         import numpy as np
@@ -234,6 +252,41 @@ class Handle:
                                                   ctypes.c_void_p(targets.data_ptr()), feats.shape[0], quantile,
                                                   lr, ctypes.c_void_p(loss.data_ptr()), self._stream()))
         return loss
+
+    def pivot_add_examples(self, dist, k: int):
+        """Appends one training example (features, standardised exact k-th
+        value) per row of a 2-D FP32 device matrix; returns the example count."""
+        rows, cols = dist.shape
+        self._check(self.lib.knn_pivot_add_examples(self.h, ctypes.c_void_p(dist.data_ptr()), rows, cols,
+                                                    max(dist.stride(0), cols), k, self._stream()))
+        return self.pivot_example_count()
+
+    def pivot_example_count(self) -> int:
+        c = ctypes.c_int64()
+        self._check(self.lib.knn_pivot_example_count(self.h, ctypes.byref(c)))
+        return int(c.value)
+
+    def pivot_examples(self):
+        """The stored examples: (features [n, 8], targets [n]) device tensors."""
+        torch = _torch()
+        n = self.pivot_example_count()
+        f = torch.empty((max(n, 1), 8), dtype=torch.float32, device=f"cuda:{self.device}")
+        y = torch.empty((max(n, 1),), dtype=torch.float32, device=f"cuda:{self.device}")
+        torch.cuda.synchronize(self.device)
+        self._check(self.lib.knn_pivot_get_examples(self.h, ctypes.c_void_p(f.data_ptr()),
+                                                    ctypes.c_void_p(y.data_ptr()), max(n, 1)))
+        return f[:n], y[:n]
+
+    def pivot_clear_examples(self):
+        self._check(self.lib.knn_pivot_clear_examples(self.h))
+
+    def pivot_train(self, out_path=None, seed: int = 1000, steps: int = 3000):
+        """Trains the pivot network on the stored examples (all on the device);
+        writes the weights file when out_path is given."""
+        torch = _torch()
+        torch.cuda.synchronize(self.device)
+        self._check(self.lib.knn_pivot_train(self.h, None if out_path is None else str(out_path).encode(),
+                                             int(seed), int(steps)))
 
     def graph(self, points, k: int, pivot="sample", precision="fp32", oversample=4, flags=0):
         """k-NN graph of the rows of `points` (own index excluded).

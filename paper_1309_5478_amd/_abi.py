@@ -20,6 +20,7 @@ FLAG_UNFUSED = 0x2
 FLAG_TIMING = 0x4
 FLAG_NO_GRAPH = 0x8
 FLAG_AUTOTUNE = 0x10
+FLAG_FORCE_RERUN = 0x20
 PIVOT_NPARAM = 4801
 
 
@@ -41,7 +42,8 @@ class Stats(ctypes.Structure):
                 ("first_pass_survivors", ctypes.c_int64), ("fallback_rows", ctypes.c_int64),
                 ("candidates_total", ctypes.c_int64), ("phase_cycles", ctypes.c_int64 * 4),
                 ("product_ms", ctypes.c_double), ("product_launches", ctypes.c_int64),
-                ("product_flops", ctypes.c_double), ("rows_uncertified", ctypes.c_int64)]
+                ("product_flops", ctypes.c_double), ("rows_uncertified", ctypes.c_int64),
+                ("rows_rerun", ctypes.c_int64)]
 
     def as_dict(self):
         d = {name: int(getattr(self, name)) for name, _ in self._fields_
@@ -69,6 +71,7 @@ PROTOTYPES = {
     "knn_batch_search": (_ST, [_P, ctypes.POINTER(Job), _I32, _P, ctypes.POINTER(Options)]),
     "knn_distances": (_ST, [_P, _P, _I64, _P, _I64, _I32, _P, _I64, _P]),
     "knn_get_stats": (_ST, [_P, ctypes.POINTER(Stats)]),
+    "knn_quantize": (_ST, [_P, _P, _I64, _I32, _I32, _P, _P, _P]),
     "knn_pivot_set_weights": (_ST, [_P, _P, _I32]),
     "knn_pivot_get_weights": (_ST, [_P, _P, _I32]),
     "knn_pivot_save": (_ST, [_P, ctypes.c_char_p]),
@@ -77,6 +80,11 @@ PROTOTYPES = {
     "knn_pivot_predict": (_ST, [_P, _P, _I64, _P, _P]),
     "knn_pivot_grad": (_ST, [_P, _P, _P, _I64, ctypes.c_float, _P, _P, _P]),
     "knn_pivot_train_step": (_ST, [_P, _P, _P, _I64, ctypes.c_float, ctypes.c_float, _P, _P]),
+    "knn_pivot_add_examples": (_ST, [_P, _P, _I64, _I64, _I64, _I32, _P]),
+    "knn_pivot_clear_examples": (_ST, [_P]),
+    "knn_pivot_example_count": (_ST, [_P, ctypes.POINTER(_I64)]),
+    "knn_pivot_get_examples": (_ST, [_P, _P, _P, _I64]),
+    "knn_pivot_train": (_ST, [_P, ctypes.c_char_p, ctypes.c_uint64, _I32]),
 }
 
 _lib = None

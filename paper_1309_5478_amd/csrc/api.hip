@@ -42,6 +42,7 @@ void add_host_stats(knn_handle_t h, int64_t rows, int64_t fallback_rows) {
     h->host_rows += rows;
     h->host_fallback += fallback_rows;
 }
+void add_host_rerun(knn_handle_t h, int64_t rows) { h->host_rerun += rows; }
 void add_product_time(knn_handle_t h, double ms, double flops) {
     h->host_product_ms += ms;
     h->host_product_flops += flops;
@@ -134,7 +135,7 @@ knn_status_t knn_destroy(knn_handle_t h) {
     if (h->stats_dev) hipFree(h->stats_dev);
     if (h->pinned) hipHostFree(h->pinned);
     for (void *p : {(void *)h->net_theta, (void *)h->net_theta_r, (void *)h->net_m, (void *)h->net_v,
-                    (void *)h->net_grad, (void *)h->net_bf16})
+                    (void *)h->net_grad, (void *)h->net_bf16, (void *)h->ex_x, (void *)h->ex_y})
         if (p) hipFree(p);
     delete h;
     return KNN_SUCCESS;
@@ -147,6 +148,7 @@ static knn_status_t begin_stats(knn_handle_t h, hipStream_t stream) {
     h->stats_pending = true;
     h->host_rows = 0;
     h->host_fallback = 0;
+    h->host_rerun = 0;
     h->host_product_ms = 0;
     h->host_product_flops = 0;
     h->host_product_launches = 0;
@@ -321,6 +323,22 @@ knn_status_t knn_distances(knn_handle_t h, const float *queries, int64_t m, cons
     return KNN_SUCCESS;
 }
 
+knn_status_t knn_quantize(knn_handle_t h, const float *X, int64_t n, int32_t d, int32_t prec, void *out, float *scale,
+                          void *stream_) {
+    if (!h) return fail(nullptr, KNN_ERROR_INVALID_VALUE, "knn_quantize: handle is null");
+    if (n < 0) return fail(h, KNN_ERROR_INVALID_VALUE, "knn_quantize: n < 0");
+    if (d < 1) return fail(h, KNN_ERROR_INVALID_VALUE, "knn_quantize: d < 1");
+    if (prec != KNN_PREC_BF16 && prec != KNN_PREC_FP8_E4M3)
+        return fail(h, KNN_ERROR_INVALID_VALUE, "knn_quantize: precision must be BF16 or FP8 e4m3");
+    if (n == 0) return KNN_SUCCESS;
+    if (!X || !out || (prec == KNN_PREC_FP8_E4M3 && !scale))
+        return fail(h, KNN_ERROR_INVALID_VALUE, "knn_quantize: null pointer");
+    hipSetDevice(h->device);
+    hipError_t e = launch_quantize(X, n, d, prec, out, scale, static_cast<hipStream_t>(stream_));
+    if (e != hipSuccess) return hip_fail(h, e, "quantize kernel");
+    return KNN_SUCCESS;
+}
+
 knn_status_t knn_get_stats(knn_handle_t h, knn_stats_t *out) {
     if (!h || !out) return fail(h, KNN_ERROR_INVALID_VALUE, "knn_get_stats: null argument");
     hipSetDevice(h->device);
@@ -345,6 +363,7 @@ knn_status_t knn_get_stats(knn_handle_t h, knn_stats_t *out) {
         t.product_flops = h->host_product_flops;
         t.product_launches = h->host_product_launches;
         t.rows_uncertified = (int64_t)s[kStatUncertified];
+        t.rows_rerun = h->host_rerun;
         t.candidates_total = (int64_t)s[kStatCandidates];
         t.phase_cycles[0] = (int64_t)s[kStatCycSample];
         t.phase_cycles[1] = (int64_t)s[kStatCycStream];

@@ -40,6 +40,7 @@ namespace knn {
 knn_status_t fail_msg(knn_handle_t h, knn_status_t s, const std::string &msg);
 unsigned long long *stats_ptr(knn_handle_t h);
 void add_host_stats(knn_handle_t h, int64_t rows, int64_t fallback_rows);
+void add_host_rerun(knn_handle_t h, int64_t rows);
 int handle_num_cu(knn_handle_t h);
 const uint16_t *handle_net(knn_handle_t h);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t stream);
@@ -81,6 +82,8 @@ struct BatchPart {
     int32_t *flags = nullptr;
     float *sv = nullptr;   // mb x kk selected candidates
     int32_t *si = nullptr;
+    int32_t *ulist = nullptr;  // FP32: uncertified rows, re-run exactly
+    float *tfix = nullptr;
 };
 
 // A multi-matrix selection launch: its segments and the segment of each row.
@@ -106,6 +109,7 @@ struct BatchShared {
     DistArgs *table = nullptr, *probe = nullptr, *stable = nullptr;
     GemmItem *items = nullptr, *sitems = nullptr;
     uint32_t *nflag = nullptr;
+    uint32_t *nu = nullptr;  // uncertified-row counts, one per part
 };
 
 // State of the last batch of a handle: its workspace, plan and graphs.
@@ -113,7 +117,7 @@ struct BatchState {
     std::vector<uint8_t> key;
     void *ws = nullptr;
     size_t ws_bytes = 0;
-    uint32_t *nflag_host = nullptr;  // pinned, one count per part
+    uint32_t *nflag_host = nullptr;  // pinned: per part the flagged-row count, then the uncertified-row count
     size_t nflag_host_cap = 0;
     hipStream_t cap_stream = nullptr;
     std::vector<hipGraphExec_t> graphs;  // in launch order, see the segments
@@ -334,6 +338,11 @@ size_t carve_batch(Carve &c, BatchState &b, int num_cu, bool probe) {
         pt.sv = c.take<float>((size_t)pt.mb * p.kk);
         pt.si = c.take<int32_t>((size_t)pt.mb * p.kk);
     }
+    for (BatchPart &pt : b.parts) {
+        if (b.jobs[pt.job].p.prec != kPrecF32) continue;
+        pt.ulist = c.take<int32_t>((size_t)pt.mb);
+        pt.tfix = c.take<float>((size_t)pt.mb);
+    }
     plan_selects(b);
     for (SegLaunch &L : b.sample_sel) {
         selws = std::max(selws, select_ws_bytes(L.cap, L.cols, select_grid(L.cap, L.rows, num_cu)));
@@ -359,6 +368,7 @@ size_t carve_batch(Carve &c, BatchState &b, int num_cu, bool probe) {
     s.sitems = c.take<GemmItem>(std::max<size_t>(si.size(), 1));
     b.nsitems = si.size();
     s.nflag = c.take<uint32_t>(b.parts.size());
+    s.nu = c.take<uint32_t>(b.parts.size());
     return c.off;
 }
 
@@ -418,6 +428,25 @@ SelectArgs seg_select_args(const BatchState &b, const SegLaunch &L) {
     return a;
 }
 
+// Certificate of a part's kk candidates (FP32: uncertified rows are listed for
+// the exact re-run), then the exact re-rank.
+hipError_t certify_rerank(const BatchState &b, knn_handle_t h, size_t pi, const float *keys, const int32_t *cidx,
+                          hipStream_t s) {
+    const BatchPart &pt = b.parts[pi];
+    const BatchJob &js = b.jobs[pt.job];
+    const Plan &p = js.p;
+    hipError_t e = hipSuccess;
+    if (p.kk < p.n_eff) {
+        CertifyArgs ca{keys, pt.mb, p.kk, js.k, js.qn2 + pt.i0, js.cmax2, p.rel, p.gamma,
+                       stats_ptr(h) + kStatUncertified, pt.ulist, b.sh.nu + pi, pt.tfix,
+                       pt.ulist != nullptr && p.force_rerun};
+        if ((e = launch_certify(ca, s)) != hipSuccess) return e;
+    }
+    RerankArgs rr{js.Q + pt.i0 * js.d, pt.mb, js.C, js.n, js.d, cidx, (uint32_t)p.kk, js.k,
+                  js.out_dist + pt.i0 * js.k, js.out_idx + pt.i0 * js.k, js.graph ? pt.i0 : -1};
+    return launch_rerank(rr, s);
+}
+
 // ---- the phases, enqueued on a stream (captured or eager) ------------------
 hipError_t enqueue_prep(const BatchState &b, knn_handle_t h, int num_cu, hipStream_t s) {
     hipError_t e = hipSuccess;
@@ -426,6 +455,7 @@ hipError_t enqueue_prep(const BatchState &b, knn_handle_t h, int num_cu, hipStre
     do {                                           \
         if ((e = (call)) != hipSuccess) return e;  \
     } while (0)
+    BTRY(launch_fill_u32(sh.nu, (int64_t)b.parts.size(), 0u, s));
     // per job: norms, quantised copies, the gathered threshold sample
     for (int j : b.order) {
         const BatchJob &js = b.jobs[j];
@@ -457,17 +487,8 @@ hipError_t enqueue_prep(const BatchState &b, knn_handle_t h, int num_cu, hipStre
         BTRY(launch_select(sa, L.cap, select_grid(L.cap, L.rows, num_cu), sh.selws, s));
     }
     // parts whose sample is the whole corpus: certificate and re-rank now
-    for (const BatchPart &pt : b.parts) {
-        if (!pt.direct) continue;
-        const BatchJob &js = b.jobs[pt.job];
-        const Plan &p = js.p;
-        if (p.kk < p.n_eff)
-            BTRY(launch_certify(pt.tv, pt.mb, p.kk, js.k, js.qn2 + pt.i0, js.cmax2, p.rel,
-                                stats_ptr(h) + kStatUncertified, s));
-        RerankArgs rr{js.Q + pt.i0 * js.d, pt.mb, js.C, js.n, js.d, pt.ti, (uint32_t)p.kk, js.k,
-                      js.out_dist + pt.i0 * js.k, js.out_idx + pt.i0 * js.k};
-        BTRY(launch_rerank(rr, s));
-    }
+    for (size_t pi = 0; pi < b.parts.size(); ++pi)
+        if (b.parts[pi].direct) BTRY(certify_rerank(b, h, pi, b.parts[pi].tv, b.parts[pi].ti, s));
     if (sh.cnt_rows) BTRY(launch_fill_u32(sh.cnt_all, sh.cnt_rows, 0u, s));
     return e;
 }
@@ -507,18 +528,11 @@ hipError_t enqueue_final(const BatchState &b, knn_handle_t h, int num_cu, hipStr
         SelectArgs ka = seg_select_args(b, b.keys_sel);
         BTRY(launch_select_keys(ka, b.sh.selws, ka.rows, num_cu, s));
     }
-    for (const BatchPart &pt : b.parts) {
-        if (pt.direct) continue;
-        const BatchJob &js = b.jobs[pt.job];
-        const Plan &p = js.p;
-        if (p.kk < p.n_eff)
-            BTRY(launch_certify(pt.sv, pt.mb, p.kk, js.k, js.qn2 + pt.i0, js.cmax2, p.rel,
-                                stats_ptr(h) + kStatUncertified, s));
-        RerankArgs rr{js.Q + pt.i0 * js.d, pt.mb, js.C, js.n, js.d, pt.si, (uint32_t)p.kk, js.k,
-                      js.out_dist + pt.i0 * js.k, js.out_idx + pt.i0 * js.k};
-        BTRY(launch_rerank(rr, s));
-    }
-    return e;
+    for (size_t pi = 0; pi < b.parts.size(); ++pi)
+        if (!b.parts[pi].direct) BTRY(certify_rerank(b, h, pi, b.parts[pi].sv, b.parts[pi].si, s));
+    // the uncertified-row counts, for the exact re-run that follows
+    return hipMemcpyAsync(b.nflag_host + b.parts.size(), b.sh.nu, b.parts.size() * sizeof(uint32_t),
+                          hipMemcpyDeviceToHost, s);
 }
 
 // Exact re-do of the flagged rows of every part (after the flag counts reached
@@ -558,6 +572,65 @@ hipError_t run_fallback(const BatchState &b, int num_cu, hipStream_t s, int64_t 
             BTRY(launch_dist_gemm(da, kEpiDense, s));
             BTRY(select_dense(sh.Df, fb, js.n, js.n, p.kk, sh.fv, sh.fi, sh.selws, num_cu, b.smode, b.net, s));
             BTRY(launch_scatter_fallback(pt.flags + f0, fb, sh.fv, sh.fi, p.kk, pt.cand, pt.cnt, p.cap, s));
+        }
+    }
+    return e;
+}
+// Exact re-run of the uncertified FP32 rows of every part (after their counts
+// reached the host): from the part's sample distances when the sample is the
+// whole corpus, else from rows materialised here.
+hipError_t run_rerun(const BatchState &b, hipStream_t s, int64_t *total) {
+    hipError_t e = hipSuccess;
+    const BatchShared &sh = b.sh;
+    const uint32_t *counts = b.nflag_host + b.parts.size();
+    for (size_t pi = 0; pi < b.parts.size(); ++pi) {
+        const int64_t nu = counts[pi];
+        if (nu == 0) continue;
+        *total += nu;
+        const BatchPart &pt = b.parts[pi];
+        const BatchJob &js = b.jobs[pt.job];
+        const Plan &p = js.p;
+        const float *Qb = js.Q + pt.i0 * js.d;
+        FixupArgs fx{};
+        fx.tfix = pt.tfix;
+        fx.Q = Qb;
+        fx.C = js.C;
+        fx.n = js.n;
+        fx.d = js.d;
+        fx.k = js.k;
+        fx.self_offset = js.graph ? pt.i0 : -1;
+        fx.out_dist = js.out_dist + pt.i0 * js.k;
+        fx.out_idx = js.out_idx + pt.i0 * js.k;
+        if (pt.direct) {
+            fx.D = pt.Ds;
+            fx.ldd = p.S;
+            fx.by_row = true;
+            fx.rows = pt.ulist;
+            fx.nrows = nu;
+            BTRY(launch_fixup(fx, s));
+            continue;
+        }
+        for (int64_t f0 = 0; f0 < nu; f0 += p.Fb) {
+            const int64_t fb = nu - f0 < p.Fb ? nu - f0 : p.Fb;
+            BTRY(launch_gather_rows(Qb, pt.mb, js.d, pt.ulist + f0, fb, sh.Qf, nullptr, nullptr, s));
+            DistArgs da{};
+            da.Q = sh.Qf;
+            da.m = fb;
+            da.C = js.C;
+            da.n = js.n;
+            da.d = js.d;
+            da.cnorm = js.cnorm;
+            da.self_offset = js.graph ? pt.i0 : -1;
+            da.row_ids = pt.ulist + f0;
+            da.out = sh.Df;
+            da.ldo = js.n;
+            BTRY(launch_dist_gemm(da, kEpiDense, s));
+            fx.D = sh.Df;
+            fx.ldd = js.n;
+            fx.by_row = false;
+            fx.rows = pt.ulist + f0;
+            fx.nrows = fb;
+            BTRY(launch_fixup(fx, s));
         }
     }
     return e;
@@ -703,7 +776,8 @@ knn_status_t run_batch(knn_handle_t h, const knn_job_t *jobs, int32_t njobs, hip
             if (b.nflag_host) hipHostFree(b.nflag_host);
             b.nflag_host = nullptr;
             b.nflag_host_cap = 0;
-            if (hipHostMalloc(&b.nflag_host, b.parts.size() * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+            if (hipHostMalloc(&b.nflag_host, 2 * b.parts.size() * sizeof(uint32_t), hipHostMallocDefault) !=
+                hipSuccess) {
                 b.nflag_host = nullptr;
                 (void)hipGetLastError();
                 return fail_msg(h, KNN_ERROR_OUT_OF_MEMORY, "knn_batch_search: pinned host buffer");
@@ -851,8 +925,14 @@ knn_status_t run_batch(knn_handle_t h, const knn_job_t *jobs, int32_t njobs, hip
         KTRY(enqueue_final(b, h, num_cu, stream));
     else
         KTRY(hipGraphLaunch(b.graphs.back(), stream));
+    int64_t rerun = 0;
+    if (b.jobs[0].p.prec == kPrecF32) {
+        KTRY(hipStreamSynchronize(stream));
+        KTRY(run_rerun(b, stream, &rerun));
+    }
 #undef KTRY
     add_host_stats(h, rows, fallback);
+    add_host_rerun(h, rerun);
     return KNN_SUCCESS;
 }
 

@@ -501,11 +501,14 @@ __global__ __launch_bounds__(kRerankThreads) void rerank_kernel(RerankArgs a) {
     const float *q = a.Q + i * a.d;
     const uint32_t kk = a.kk;
     const int32_t *ci = a.cidx + i * kk;
+    const int64_t own = a.self_offset >= 0 ? a.self_offset + i : (int64_t)-1;
     for (uint32_t c0 = wave * PPW + grp; c0 < kk; c0 += 2 * STEP) {
         const uint32_t c1 = c0 + STEP;
         const uint32_t j0 = (uint32_t)ci[c0];
         const uint32_t j1 = c1 < kk ? (uint32_t)ci[c1] : 0xFFFFFFFFu;
-        const bool ok0 = (int64_t)j0 < a.n, ok1 = (int64_t)j1 < a.n;  // missing candidates: never for valid lists
+        // missing candidates (never for valid lists) and the query's own index
+        // (a candidate only when its row has no other finite key) are dropped
+        const bool ok0 = (int64_t)j0 < a.n && (int64_t)j0 != own, ok1 = (int64_t)j1 < a.n && (int64_t)j1 != own;
         float s0 = ok0 ? rerank_dist<G, VEC>(q, a.C + (int64_t)j0 * a.d, a.d, sub) : 0.f;
         float s1 = ok1 ? rerank_dist<G, VEC>(q, a.C + (int64_t)j1 * a.d, a.d, sub) : 0.f;
 #pragma unroll
@@ -534,10 +537,12 @@ __global__ __launch_bounds__(kRerankThreads) void rerank_kernel(RerankArgs a) {
 
 // ---- reduced-precision operands ---------------------------------------------
 // OCP e4m3 (1 sign, 4 exponent bits with bias 7, 3 mantissa bits, no infinity),
-// round to nearest even, saturating at +-448 (also for infinities).
+// round to nearest even, saturating at +-448 (also for infinities); a NaN
+// becomes the NaN code S.1111.111.
 __device__ __forceinline__ uint8_t f32_to_e4m3(float x) {
     const uint8_t sign = (uint8_t)((__float_as_uint(x) >> 24) & 0x80u);
     const float a = fabsf(x);
+    if (a != a) return sign | 0x7Fu;
     if (!(a < 448.0f)) return sign | 0x7Eu;
     if (a < 0.015625f) {                               // below 2^-6: subnormals, step 2^-9
         return sign | (uint8_t)rintf(a * 512.0f);      // 8 (= 2^-6) encodes the smallest normal
@@ -552,14 +557,20 @@ __device__ __forceinline__ uint8_t f32_to_e4m3(float x) {
     return sign | (uint8_t)(((e + 7) << 3) | ((int)r - 8));
 }
 
+// BF16 by round to nearest even on the low 16 bits; a NaN stays a quiet NaN
+// (the rounding carry could otherwise turn a NaN with only low payload bits
+// into an infinity).
 __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
     uint32_t u = __float_as_uint(f);
+    if (f != f) return (uint16_t)((u >> 16) | 0x40u);
     u += 0x7FFFu + ((u >> 16) & 1u);
     return (uint16_t)(u >> 16);
 }
 
-// One wave per point.  FP8: e = the largest integer with amax * 2^e <= 448
-// (0 for an all-zero point), elements x * 2^e rounded to e4m3, scale 2^-e.
+// One wave per point.  FP8: e = the largest integer with amax * 2^e <= 448,
+// amax the largest finite magnitude of the point (e = 0 without a finite
+// non-zero element; e limited to [-100, 100]), elements x * 2^e rounded to
+// e4m3, scale 2^-e.
 __global__ __launch_bounds__(256) void quantize_kernel(const float *__restrict__ X, int64_t n, int d, int prec, int dq,
                                                        void *__restrict__ out, float *__restrict__ scale_out) {
     const int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.x / kWave;
@@ -572,14 +583,19 @@ __global__ __launch_bounds__(256) void quantize_kernel(const float *__restrict__
         return;
     }
     float amax = 0.f;
-    for (int t = lane; t < d; t += kWave) amax = fmaxf(amax, fabsf(x[t]));
+    for (int t = lane; t < d; t += kWave) {
+        const float v = fabsf(x[t]);
+        if (v <= 3.4028235e38f) amax = fmaxf(amax, v);  // finite magnitudes only
+    }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off));
     int e = 0;
-    if (amax > 0.f && amax < 3.0e38f) {
-        e = (int)floorf(log2f(448.0f / amax));
-        while (ldexpf(amax, e + 1) <= 448.0f) ++e;
-        while (ldexpf(amax, e) > 448.0f) --e;
+    if (amax > 0.f) {
+        // amax = f 2^E with f in [0.5, 1): amax 2^e <= 448 = 0.875 * 2^9 exactly
+        // when e <= 9 - E, less one when f > 0.875
+        int E;
+        const float f = frexpf(amax, &E);
+        e = 9 - E - (f > 0.875f ? 1 : 0);
         e = e < -100 ? -100 : (e > 100 ? 100 : e);
     }
     uint8_t *o = static_cast<uint8_t *>(out) + i * dq;
@@ -587,24 +603,127 @@ __global__ __launch_bounds__(256) void quantize_kernel(const float *__restrict__
     if (lane == 0) scale_out[i] = ldexpf(1.0f, -e);
 }
 
-// Largest value of a non-negative array into *out (float bits compare as ints).
-// A row's kk candidates are certified to contain its true k nearest when the
-// gap between the kk-th and the k-th candidate key exceeds twice the key error
-// bound E_i = 2 rel ||q_i|| max_j ||c_j|| (Cauchy-Schwarz on the dot-product
-// error).
-__global__ __launch_bounds__(256) void certify_kernel(const float *__restrict__ sk, int64_t m, int kk, int k,
-                                                      const float *__restrict__ qn2,
-                                                      const unsigned int *__restrict__ cmax2_bits, float rel,
-                                                      unsigned long long *__restrict__ count) {
+// Per-row candidate certificate (see launch_certify in dist.hpp for the bound).
+__global__ __launch_bounds__(256) void certify_kernel(CertifyArgs a) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     bool bad = false;
-    if (i < m) {
-        const float gap = sk[i * kk + kk - 1] - sk[i * kk + k - 1];
-        const float E = 2.0f * rel * sqrtf(qn2[i]) * sqrtf(__uint_as_float(*cmax2_bits));
-        bad = !(gap > 2.0f * E);
+    if (i < a.m) {
+        const float ak = a.sorted_keys[i * a.kk + a.k - 1];
+        const float gap = a.sorted_keys[i * a.kk + a.kk - 1] - ak;
+        const float c2 = __uint_as_float(*a.cmax2_bits), cm = sqrtf(c2), qm = sqrtf(a.qnorm2[i]);
+        constexpr float u2 = 2.0f * 5.9604645e-8f;  // 2^-23
+        // 1.001: slack for the FP32 evaluation of the bound itself
+        const float E = 1.001f * ((a.gamma + u2) * c2 + 2.0f * (a.rel + u2) * qm * cm);
+        bad = a.force || !(gap > 2.0f * E);
+        if (bad && a.list) {
+            const uint32_t p = atomicAdd(a.nlist, 1u);
+            a.list[p] = (int32_t)i;
+            a.tfix[i] = ak + 2.0f * E;
+        }
     }
     const uint64_t b = __ballot(bad);
-    if (lane_id() == 0 && b) atomicAdd(count, (unsigned long long)__popcll(b));
+    if (lane_id() == 0 && b) atomicAdd(a.count, (unsigned long long)__popcll(b));
+}
+
+// ---- exact re-run of uncertified rows ------------------------------------------
+// One workgroup per listed row.  The row's reduced keys are scanned in tiles of
+// 1024; columns at or below the threshold are compacted into LDS (ballot +
+// population count, one LDS reservation per wave) and, once 1024 or more are
+// pending, re-ranked by exact distance, sorted and merged into the running
+// 1024 smallest (distance, index) keys: the elementwise minimum of the
+// ascending running list and the reversed lower half of the sorted batch holds
+// exactly the 1024 smallest of both, as a bitonic sequence, which ten
+// half-cleaning steps sort.
+constexpr int kFixThreads = 256;
+constexpr int kFixTop = 1024;
+constexpr int kFixBatch = 2048;
+
+template <int G, bool VEC>
+__global__ __launch_bounds__(kFixThreads) void exact_rows_kernel(FixupArgs a) {
+    constexpr uint32_t PPW = kWave / G;
+    constexpr uint32_t STEP = (kFixThreads / kWave) * PPW;
+    __shared__ uint64_t top[kFixTop];
+    __shared__ uint64_t batch[kFixBatch];
+    __shared__ uint32_t cidx[kFixBatch];
+    __shared__ uint32_t cnt;
+    const int64_t f = blockIdx.x;
+    if (f >= a.nrows) return;
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave, sub = lane % G, grp = lane / G;
+    const int64_t i = a.rows[f];
+    const float *drow = a.D + (a.by_row ? i : f) * a.ldd;
+    const float T = a.tfix[i];
+    const bool bounded = fabsf(T) <= 3.4028235e38f;  // finite (false for NaN)
+    const float *q = a.Q + i * a.d;
+    const int64_t own = a.self_offset >= 0 ? a.self_offset + i : (int64_t)-1;
+    for (uint32_t t = tid; t < (uint32_t)kFixTop; t += kFixThreads) top[t] = kKeyMax;
+    if (tid == 0) cnt = 0;
+    __syncthreads();
+
+    auto flush = [&](uint32_t c) {
+        for (uint32_t c0 = wave * PPW + grp; c0 < c; c0 += STEP) {
+            const uint32_t j = cidx[c0];
+            float s = rerank_dist<G, VEC>(q, a.C + (int64_t)j * a.d, a.d, sub);
+#pragma unroll
+            for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off);
+            if (sub == 0) batch[c0] = (int64_t)j == own ? kKeyMax : make_key(s, j);
+        }
+        for (uint32_t t = c + tid; t < (uint32_t)kFixTop; t += kFixThreads) batch[t] = kKeyMax;
+        __syncthreads();
+        block_sort<kFixThreads, 8>(batch, c < (uint32_t)kFixTop ? (uint32_t)kFixTop : c);
+        for (uint32_t t = tid; t < (uint32_t)kFixTop; t += kFixThreads) {
+            const uint64_t x = top[t], y = batch[kFixTop - 1 - t];
+            top[t] = x < y ? x : y;
+        }
+        __syncthreads();
+        for (uint32_t st = kFixTop / 2; st > 0; st >>= 1) {
+            for (uint32_t t = tid; t < (uint32_t)kFixTop / 2; t += kFixThreads) {
+                const uint32_t lo = (t / st) * 2 * st + t % st, hi = lo + st;
+                const uint64_t x = top[lo], y = top[hi];
+                if (y < x) {
+                    top[lo] = y;
+                    top[hi] = x;
+                }
+            }
+            __syncthreads();
+        }
+    };
+
+    constexpr uint32_t kTileCols = 4 * kFixThreads;
+    for (int64_t j0 = 0; j0 < a.n; j0 += kTileCols) {
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u) {
+            const int64_t j = j0 + u * kFixThreads + tid;
+            const bool valid = j < a.n;
+            const float v = valid ? drow[j] : 0.f;
+            const bool pass = valid && (!bounded || v <= T);
+            const uint64_t m = __ballot(pass);
+            if (m) {
+                uint32_t base = 0;
+                if (lane == 0) base = atomicAdd(&cnt, (uint32_t)__popcll(m));
+                base = wave_bcast0(base);
+                if (pass) cidx[base + lanes_below(m)] = (uint32_t)j;
+            }
+        }
+        __syncthreads();
+        const uint32_t c = cnt;
+        __syncthreads();
+        if (c > 0 && (c >= (uint32_t)kFixTop || j0 + kTileCols >= a.n)) {
+            flush(c);
+            if (tid == 0) cnt = 0;
+            __syncthreads();
+        }
+    }
+    for (uint32_t t = tid; t < (uint32_t)a.k; t += kFixThreads) {
+        const uint64_t key = top[t];
+        const int64_t o = i * a.k + t;
+        if (key == kKeyMax) {
+            a.out_dist[o] = __uint_as_float(0x7f800000u);
+            a.out_idx[o] = -1;
+        } else {
+            a.out_dist[o] = ord_to_float(key_ord(key));
+            a.out_idx[o] = (int32_t)key_idx(key);
+        }
+    }
 }
 
 // ---- host launchers ----------------------------------------------------------
@@ -784,11 +903,35 @@ hipError_t launch_quantize(const float *X, int64_t n, int d, int prec, void *out
     return hipGetLastError();
 }
 
-hipError_t launch_certify(const float *sorted_keys, int64_t m, int kk, int k, const float *qnorm2,
-                          const unsigned int *cmax2_bits, float rel, unsigned long long *count, hipStream_t stream) {
-    if (m == 0) return hipSuccess;
-    hipLaunchKernelGGL(certify_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, stream, sorted_keys, m, kk, k,
-                       qnorm2, cmax2_bits, rel, count);
+hipError_t launch_certify(const CertifyArgs &a, hipStream_t stream) {
+    if (a.m == 0) return hipSuccess;
+    hipLaunchKernelGGL(certify_kernel, dim3((unsigned)((a.m + 255) / 256)), dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
+
+template <int G>
+static void launch_fixup_g(const FixupArgs &a, bool vec, hipStream_t stream) {
+    if (vec)
+        hipLaunchKernelGGL((exact_rows_kernel<G, true>), dim3((unsigned)a.nrows), dim3(kFixThreads), 0, stream, a);
+    else
+        hipLaunchKernelGGL((exact_rows_kernel<G, false>), dim3((unsigned)a.nrows), dim3(kFixThreads), 0, stream, a);
+}
+
+hipError_t launch_fixup(const FixupArgs &a, hipStream_t stream) {
+    if (a.nrows == 0) return hipSuccess;
+    if (a.k < 1 || a.k > kFixTop || a.nrows > 0x7fffffff) return hipErrorInvalidValue;
+    // the same lane grouping as the re-rank, so a pair's distance has the same bits
+    const bool vec = a.d % 4 == 0 && (reinterpret_cast<uintptr_t>(a.Q) & 15u) == 0 &&
+                     (reinterpret_cast<uintptr_t>(a.C) & 15u) == 0;
+    switch (lanes_for(a.d, vec)) {
+        case 1: launch_fixup_g<1>(a, vec, stream); break;
+        case 2: launch_fixup_g<2>(a, vec, stream); break;
+        case 4: launch_fixup_g<4>(a, vec, stream); break;
+        case 8: launch_fixup_g<8>(a, vec, stream); break;
+        case 16: launch_fixup_g<16>(a, vec, stream); break;
+        case 32: launch_fixup_g<32>(a, vec, stream); break;
+        default: launch_fixup_g<64>(a, vec, stream); break;
+    }
     return hipGetLastError();
 }
 

@@ -60,6 +60,7 @@ struct RerankArgs {
     int k;
     float *out_dist;        // m x k
     int32_t *out_idx;       // m x k
+    int64_t self_offset = -1;  // >= 0: row i's own corpus index self_offset + i is never returned
 };
 
 hipError_t launch_dist_gemm(const DistArgs &a, int epi, hipStream_t stream);
@@ -93,10 +94,53 @@ hipError_t launch_rerank(const RerankArgs &a, hipStream_t stream);
 // elements; scale_out (FP8 only) receives 2^-e per row.
 hipError_t launch_quantize(const float *X, int64_t n, int d, int prec, void *out, float *scale_out,
                            hipStream_t stream);
-// Per-row certificate of a candidate list: the row is certified when the gap
-// between its kk-th and k-th candidate keys exceeds twice the bound on the key
-// error, 2 rel ||q_i|| max_j ||c_j||; uncertified rows are counted into *count.
-hipError_t launch_certify(const float *sorted_keys, int64_t m, int kk, int k, const float *qnorm2,
-                          const unsigned int *cmax2_bits, float rel, unsigned long long *count, hipStream_t stream);
+// Per-row certificate of a candidate list.  The reduced key of column j,
+// ||c_j||^2 - 2 q_i.c_j, is computed with an error of at most
+//   E_i = (gamma + 2u) max ||c||^2 + 2 (rel + 2u) ||q_i|| max ||c||
+// (gamma: the FP32 norm reduction over d terms; rel: the relative error of the
+// dot product in the operand precision; 2u: the final fused multiply-add).  A row
+// is certified when the gap between its kk-th and k-th candidate keys exceeds
+// 2 E_i: then every point outside the candidates has a larger exact key than the
+// k-th candidate, so the exact top k lie among the candidates.  Uncertified rows
+// are counted into *count and, when `list` is set, appended to list (count in
+// *nlist) with the threshold key_k + 2 E_i in tfix[i], which bounds the reduced
+// key of every exact top-k point of the row (NaN or infinite when no bound
+// exists).
+struct CertifyArgs {
+    const float *sorted_keys;  // m x kk, ascending
+    int64_t m;
+    int kk, k;
+    const float *qnorm2;       // m squared query norms
+    const unsigned int *cmax2_bits;
+    float rel, gamma;
+    unsigned long long *count;
+    int32_t *list;             // or null
+    uint32_t *nlist;
+    float *tfix;               // m thresholds (only uncertified rows written)
+    int force;                 // treat every row as uncertified
+};
+hipError_t launch_certify(const CertifyArgs &a, hipStream_t stream);
+
+// Exact re-run of listed rows (uncertified FP32 rows) from their materialised
+// reduced-key rows: every column whose key is at most the row's threshold tfix
+// is re-ranked by its exact FP32 direct-form distance (the same arithmetic as
+// the re-rank), and the k smallest (distance, index) pairs are written to the
+// row's output.  Rows without a finite threshold re-rank every column.
+struct FixupArgs {
+    const float *D;          // reduced keys, row stride ldd: row f holds listed row rows[f], or
+    int64_t ldd;             // with by_row, row i holds row id i (a materialised block)
+    bool by_row;
+    const int32_t *rows;     // nrows row ids within the block
+    int64_t nrows;
+    const float *tfix;       // thresholds by row id
+    const float *Q;          // block queries, row-major (row id i at Q + i d)
+    const float *C;          // corpus n x d
+    int64_t n;
+    int d, k;
+    int64_t self_offset;     // >= 0: row i's own corpus index self_offset + i is excluded
+    float *out_dist;         // block outputs, row id i at out + i k
+    int32_t *out_idx;
+};
+hipError_t launch_fixup(const FixupArgs &a, hipStream_t stream);
 
 }  // namespace knn

@@ -20,7 +20,7 @@ struct knn_handle_s {
     hipStream_t last_stream = nullptr;
     knn_stats_t last{};
     bool stats_pending = false;
-    int64_t host_rows = 0, host_fallback = 0;  // host-side counters of the last call
+    int64_t host_rows = 0, host_fallback = 0, host_rerun = 0;  // host-side counters of the last call
     double host_product_ms = 0, host_product_flops = 0;
     int64_t host_product_launches = 0;
     uint32_t *pinned = nullptr;                 // one pinned word for device-to-host counts
@@ -32,6 +32,9 @@ struct knn_handle_s {
     int64_t net_step = 0;
     bool has_net = false;
     float net_quantile = 0.9f;
+    // training examples of the pivot network (features rows x 8, targets)
+    float *ex_x = nullptr, *ex_y = nullptr;
+    int64_t ex_n = 0, ex_cap = 0;
     // plan, workspace and graphs of the last knn_batch_search
     knn::BatchState *batch = nullptr;
 };

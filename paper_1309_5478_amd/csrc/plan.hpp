@@ -38,8 +38,10 @@ struct Plan {
     int prec;          // kPrecF32 / kPrecBF16 / kPrecFP8
     int64_t ldq;       // bytes per quantised row
     float rel;         // relative dot-product error bound of the precision
+    float gamma;       // relative error bound of an FP32 reduction over d terms
     bool graph, unfused;
     int force;
+    int force_rerun;
     // fused
     int S;
     bool gathered;
@@ -69,6 +71,9 @@ struct Bufs {
     float *Qf = nullptr, *Df = nullptr, *fv = nullptr;
     int32_t *fi = nullptr;
     float *Dm = nullptr;
+    int32_t *ulist = nullptr;  // uncertified rows of the current block (FP32 re-run)
+    uint32_t *nu = nullptr;
+    float *tfix = nullptr;
     void *selws = nullptr;
     float *ninf = nullptr;  // one -inf: threshold of the tile-timing launches
 };
@@ -92,6 +97,12 @@ inline size_t carve(Carve &c, const Plan &p, Bufs &b, int num_cu) {
         }
     }
     size_t selws = 0;
+    {
+        const int64_t rows = p.unfused ? p.Mu : p.Mb;
+        b.ulist = c.take<int32_t>((size_t)rows);
+        b.tfix = c.take<float>((size_t)rows);
+        b.nu = c.take<uint32_t>(1);
+    }
     if (p.unfused) {
         b.Dm = c.take<float>((size_t)p.Mu * p.n);
         b.sv = c.take<float>((size_t)p.Mu * p.kk);
@@ -196,6 +207,7 @@ inline Plan make_plan(int64_t m, int64_t n, int d, int k, bool graph, const knn_
     p.kk = (int)kk;
     p.unfused = opt && (opt->flags & KNN_FLAG_UNFUSED);
     p.force = (opt && (opt->flags & KNN_FLAG_FORCE_FALLBACK)) ? 1 : 0;
+    p.force_rerun = (opt && (opt->flags & KNN_FLAG_FORCE_RERUN)) ? 1 : 0;
     p.prec = opt ? opt->precision : KNN_PREC_FP32;
     {
         const int dq = (d + kQuantPad - 1) / kQuantPad * kQuantPad;
@@ -203,6 +215,7 @@ inline Plan make_plan(int64_t m, int64_t n, int d, int k, bool graph, const knn_
         const double gamma = d * std::ldexp(1.0, -24) / (1.0 - d * std::ldexp(1.0, -24));
         const double u = p.prec == kPrecBF16 ? std::ldexp(1.0, -8) : (p.prec == kPrecFP8 ? std::ldexp(1.0, -4) : 0.0);
         p.rel = (float)(2 * u + u * u + gamma);
+        p.gamma = (float)gamma;
     }
     if (p.unfused) {
         int64_t mu = (int64_t)(kDenseBytes / sizeof(float) / (size_t)n);

@@ -38,6 +38,7 @@ knn_status_t fail_msg(knn_handle_t h, knn_status_t s, const std::string &msg);
 uint32_t *host_counter(knn_handle_t h);
 unsigned long long *stats_ptr(knn_handle_t h);
 void add_host_stats(knn_handle_t h, int64_t rows, int64_t fallback_rows);
+void add_host_rerun(knn_handle_t h, int64_t rows);
 void add_product_time(knn_handle_t h, double ms, double flops);
 int handle_num_cu(knn_handle_t h);
 const uint16_t *handle_net(knn_handle_t h);
@@ -101,9 +102,77 @@ knn_status_t run_search(knn_handle_t h, const float *Q, int64_t m, const float *
     };
     auto qsrow = [&](int64_t i0) -> const float * { return qsc ? qsc + i0 : nullptr; };
     const bool certify = p.kk < p.n_eff;
-    int64_t fallback_total = 0;
+    int64_t fallback_total = 0, rerun_total = 0;
     ProductTimer timer;
     KNN_TRY(timer.init(opt && (opt->flags & KNN_FLAG_TIMING)));
+    uint32_t *hcount = host_counter(h);
+    // FP32 rows whose candidate margin is not certified are re-run exactly
+    const bool refix = certify && p.prec == kPrecF32;
+
+    // certificate and exact re-rank of one block's kk candidates (ascending
+    // reduced keys `keys`, corpus indices `cidx`), then the exact re-run of the
+    // uncertified rows, from the block's materialised reduced-key rows when
+    // there are (Dblock, row stride ldd), else from rows materialised here
+    auto finish = [&](const float *keys, const int32_t *cidx, int64_t i0, int64_t mb, const float *Dblock,
+                      int64_t ldd) -> knn_status_t {
+        const float *Qb = Q + i0 * d;
+        if (certify) {
+            if (refix) KNN_TRY(launch_fill_u32(b.nu, 1, 0u, stream));
+            CertifyArgs ca{keys, mb, p.kk, k, b.qn2 + i0, b.cmax2, p.rel, p.gamma, stats_ptr(h) + kStatUncertified,
+                           refix ? b.ulist : nullptr, b.nu, b.tfix, refix && p.force_rerun};
+            KNN_TRY(launch_certify(ca, stream));
+        }
+        RerankArgs rr{Qb, mb, C, n, d, cidx, (uint32_t)p.kk, k, out_dist + i0 * k, out_idx + i0 * k,
+                      graph ? i0 : -1};
+        KNN_TRY(launch_rerank(rr, stream));
+        if (!refix) return KNN_SUCCESS;
+        KNN_TRY(hipMemcpyAsync(hcount, b.nu, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
+        KNN_TRY(hipStreamSynchronize(stream));
+        const int64_t nu = *hcount;
+        rerun_total += nu;
+        FixupArgs fx{};
+        fx.tfix = b.tfix;
+        fx.Q = Qb;
+        fx.C = C;
+        fx.n = n;
+        fx.d = d;
+        fx.k = k;
+        fx.self_offset = graph ? i0 : -1;
+        fx.out_dist = out_dist + i0 * k;
+        fx.out_idx = out_idx + i0 * k;
+        if (Dblock) {
+            fx.D = Dblock;
+            fx.ldd = ldd;
+            fx.by_row = true;
+            fx.rows = b.ulist;
+            fx.nrows = nu;
+            KNN_TRY(launch_fixup(fx, stream));
+            return KNN_SUCCESS;
+        }
+        for (int64_t f0 = 0; f0 < nu; f0 += p.Fb) {
+            const int64_t fb = nu - f0 < p.Fb ? nu - f0 : p.Fb;
+            KNN_TRY(launch_gather_rows(Qb, mb, d, b.ulist + f0, fb, b.Qf, nullptr, nullptr, stream));
+            DistArgs da{};
+            da.Q = b.Qf;
+            da.m = fb;
+            da.C = C;
+            da.n = n;
+            da.d = d;
+            da.cnorm = b.cnorm;
+            da.self_offset = graph ? i0 : -1;
+            da.row_ids = b.ulist + f0;
+            da.out = b.Df;
+            da.ldo = n;
+            KNN_TRY(launch_dist_gemm(da, kEpiDense, stream));
+            fx.D = b.Df;
+            fx.ldd = n;
+            fx.by_row = false;
+            fx.rows = b.ulist + f0;
+            fx.nrows = fb;
+            KNN_TRY(launch_fixup(fx, stream));
+        }
+        return KNN_SUCCESS;
+    };
 
     if (p.unfused) {
         for (int64_t i0 = 0; i0 < m; i0 += p.Mu) {
@@ -123,17 +192,15 @@ knn_status_t run_search(knn_handle_t h, const float *Q, int64_t m, const float *
             KNN_TRY(launch_dist_gemm(a, kEpiDense, stream));
             KNN_TRY(timer.end(stream));
             KNN_TRY(select_dense(b.Dm, mb, n, n, p.kk, b.sv, b.si, b.selws, num_cu, smode, net, stream));
-            if (certify)
-                KNN_TRY(launch_certify(b.sv, mb, p.kk, k, b.qn2 + i0, b.cmax2, p.rel, stats_ptr(h) + kStatUncertified,
-                                       stream));
-            RerankArgs rr{Q + i0 * d, mb, C, n, d, b.si, (uint32_t)p.kk, k, out_dist + i0 * k, out_idx + i0 * k};
-            KNN_TRY(launch_rerank(rr, stream));
+            knn_status_t fs = finish(b.sv, b.si, i0, mb, b.Dm, n);
+            if (fs != KNN_SUCCESS) return fs;
             if (timer.on) {
                 KNN_TRY(hipStreamSynchronize(stream));
                 KNN_TRY(timer.collect(h));
             }
         }
         add_host_stats(h, m, 0);
+        add_host_rerun(h, rerun_total);
         return KNN_SUCCESS;
     }
 
@@ -183,7 +250,6 @@ knn_status_t run_search(knn_handle_t h, const float *Q, int64_t m, const float *
             KNN_TRY(autotune_pick(key, cands, run, stream, 2, &ftile));
         }
     }
-    uint32_t *hcount = host_counter(h);
     for (int64_t i0 = 0; i0 < m; i0 += p.Mb) {
         const int64_t mb = m - i0 < p.Mb ? m - i0 : p.Mb;
         const float *Qb = Q + i0 * d;
@@ -207,11 +273,8 @@ knn_status_t run_search(knn_handle_t h, const float *Q, int64_t m, const float *
             // the sample is the whole corpus: its selection already holds each
             // row's kk smallest keys, in order, so the filtered product, the
             // candidate lists and their selection would only repeat it
-            if (certify)
-                KNN_TRY(launch_certify(b.tv, mb, p.kk, k, b.qn2 + i0, b.cmax2, p.rel, stats_ptr(h) + kStatUncertified,
-                                       stream));
-            RerankArgs rr{Qb, mb, C, n, d, b.ti, (uint32_t)p.kk, k, out_dist + i0 * k, out_idx + i0 * k};
-            KNN_TRY(launch_rerank(rr, stream));
+            knn_status_t fs = finish(b.tv, b.ti, i0, mb, b.Ds, p.S);
+            if (fs != KNN_SUCCESS) return fs;
             if (timer.on) {
                 KNN_TRY(hipStreamSynchronize(stream));
                 KNN_TRY(timer.collect(h));
@@ -279,14 +342,12 @@ knn_status_t run_search(knn_handle_t h, const float *Q, int64_t m, const float *
         ka.out_idx = b.si;
         ka.mode = smode;
         KNN_TRY(launch_select_keys(ka, b.selws, mb, num_cu, stream));
-        if (certify)
-            KNN_TRY(launch_certify(b.sv, mb, p.kk, k, b.qn2 + i0, b.cmax2, p.rel, stats_ptr(h) + kStatUncertified,
-                                   stream));
-        RerankArgs rr{Qb, mb, C, n, d, b.si, (uint32_t)p.kk, k, out_dist + i0 * k, out_idx + i0 * k};
-        KNN_TRY(launch_rerank(rr, stream));
+        knn_status_t fs = finish(b.sv, b.si, i0, mb, nullptr, 0);
+        if (fs != KNN_SUCCESS) return fs;
     }
 #undef KNN_TRY
     add_host_stats(h, m, fallback_total);
+    add_host_rerun(h, rerun_total);
     return KNN_SUCCESS;
 }
 

@@ -3,10 +3,12 @@
 Rows: squared-distance rows produced by the library (``knn_distances``) for
 synthetic point sets of three kinds (uniform[0,1), N(0,1), 64-component Gaussian
 mixture) over a grid of corpus sizes and dimensions, drawn with seeds >= 1000
-so that they never coincide with evaluation inputs.  Targets: the exact k-th
-smallest value of each row from ``knn_select_k``, standardised with the row
-sample's median and scale, for k from 1 to 1024.  Every optimisation step runs
-the library's forward, backward and Adam kernels (``knn_pivot_train_step``).
+so that they never coincide with evaluation inputs.  For each row and each k
+from 1 to 1024 the library stores one example (``knn_pivot_add_examples``: the
+row's features and its exact k-th smallest value standardised, computed on the
+device), then trains the network from a seed (``knn_pivot_train``: He
+initialisation, batch draws, forward, backward and Adam, all on the device).
+This module only generates the point sets and calls the library.
 
     python -m paper_1309_5478_amd.pivot_train --out paper_1309_5478_amd/pivot_weights.bin
 """
@@ -20,7 +22,8 @@ import time
 import numpy as np
 
 DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "pivot_weights.bin")
-QUANTILE = 0.99
+QUANTILE = 0.99     # the training quantile of knn_pivot_train
+KS = (1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024)
 
 KINDS = ("uniform", "normal", "gmm")
 
@@ -34,28 +37,21 @@ def _points(kind, n, d, seed):
     return synth.gmm_points(n, d, seed)
 
 
-def make_rows(h, configs, rows_per_set=128, ks=(1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024), log=None):
-    """Features and standardised targets for every (point set, k) of `configs`,
-    a list of (kind, n, d, seed).  Returns device tensors (B x 8, B)."""
+def add_rows(h, configs, rows_per_set=128, ks=KS, log=None):
+    """Stores training examples for every (point set, k) of `configs`, a list
+    of (kind, n, d, seed): the distance rows of the set's first rows_per_set
+    points against the whole set.  Returns the example count."""
     import torch
-    feats, targets = [], []
     for kind, n, d, seed in configs:
         P = torch.from_numpy(_points(kind, n, d, seed)).cuda()
-        Q = P[:rows_per_set].contiguous()
-        D = h.distances(Q, P)
+        D = h.distances(P[:rows_per_set].contiguous(), P)
         for k in ks:
-            if k > n // 4:
-                continue
-            f, ms = h.pivot_features(D, k)
-            v, _ = h.select_k(D, k)
-            y = (v[:, k - 1] - ms[:, 0]) / ms[:, 1]
-            ok = torch.isfinite(y) & torch.isfinite(f).all(dim=1)
-            feats.append(f[ok])
-            targets.append(y[ok])
+            if k <= n // 4:
+                h.pivot_add_examples(D, k)
         if log:
             log(f"  rows from {kind} n={n} d={d}")
-        del D, P, Q
-    return torch.cat(feats).contiguous(), torch.cat(targets).contiguous()
+        del D, P
+    return h.pivot_example_count()
 
 
 def default_configs(seed_base=1000, big=True):
@@ -70,6 +66,8 @@ def default_configs(seed_base=1000, big=True):
 
 
 def he_init(seed: int = 1000, b3: float = 0.0) -> np.ndarray:
+    """Random parameters for tests of the kernels (host draw; training itself
+    initialises on the device)."""
     rng = np.random.default_rng(seed)
     H, NIN = 64, 8
     W1 = rng.normal(0, np.sqrt(2.0 / NIN), (H, NIN))
@@ -78,42 +76,27 @@ def he_init(seed: int = 1000, b3: float = 0.0) -> np.ndarray:
     return np.concatenate([W1.ravel(), np.zeros(H), W2.ravel(), np.zeros(H), w3, [b3]]).astype(np.float32)
 
 
-def train(h=None, out_path=DEFAULT_WEIGHTS, steps=3000, batch=4096, lr=2e-3, quantile=QUANTILE, seed=1000,
-          configs=None, log=print):
-    import torch
-
+def train(h=None, out_path=DEFAULT_WEIGHTS, steps=3000, seed=1000, configs=None, log=print):
     import paper_1309_5478_amd as knn
-    h = h or knn.Handle(0)
+    h = h or knn.Handle(0, pivot_weights=None)
     t0 = time.time()
     configs = configs if configs is not None else default_configs(seed)
-    X, Y = make_rows(h, configs, log=log)
-    log(f"{X.shape[0]} training rows in {time.time() - t0:.1f} s")
-    h.pivot_set_weights(he_init(seed, b3=float(Y.median())))
-    g = torch.Generator(device="cuda")
-    g.manual_seed(seed)
-    B = X.shape[0]
-    loss = None
-    for it in range(steps):
-        idx = torch.randint(0, B, (min(batch, B),), device="cuda", generator=g)
-        step_lr = lr * (0.1 ** (it / max(steps, 1)))          # exponential decay to lr / 10
-        loss = h.pivot_train_step(X[idx].contiguous(), Y[idx].contiguous(), quantile, step_lr)
-        if it % 500 == 0 or it == steps - 1:
-            log(f"step {it}: pinball loss {float(loss):.4f}")
-    if out_path:
-        h.pivot_save(out_path)
-        log(f"saved {out_path}")
-    return h, float(loss)
+    h.pivot_clear_examples()
+    n = add_rows(h, configs, log=log)
+    log(f"{n} training examples in {time.time() - t0:.1f} s")
+    t1 = time.time()
+    h.pivot_train(out_path, seed=seed, steps=steps)
+    log(f"{steps} training steps in {time.time() - t1:.1f} s" + (f"; saved {out_path}" if out_path else ""))
+    return h
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
     ap.add_argument("--steps", type=int, default=3000)
-    ap.add_argument("--quantile", type=float, default=QUANTILE)
     ap.add_argument("--seed", type=int, default=1000)
     args = ap.parse_args(argv)
-    train(out_path=args.out, steps=args.steps, quantile=args.quantile, seed=args.seed,
-          log=lambda *a: print(*a, file=sys.stderr, flush=True))
+    train(out_path=args.out, steps=args.steps, seed=args.seed, log=lambda *a: print(*a, file=sys.stderr, flush=True))
 
 
 if __name__ == "__main__":

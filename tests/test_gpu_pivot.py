@@ -93,6 +93,55 @@ def test_training_steps_reduce_loss(h, torch):
     assert last < 0.3 * first, (first, last)
 
 
+def test_training_examples_match_oracle(torch, knn):
+    """Examples stored from distance rows: the features and the exact k-th
+    value standardised, as the FP64 network oracle and the selection oracle
+    compute them; rows with non-finite values are skipped, order kept."""
+    hh = knn.Handle(0, pivot_weights=None)
+    D = synth.sqdist_matrix_normal(30, 3000, 16, seed=8)
+    D[4, 100] = np.nan                  # its k-th value stays finite at small k
+    D[6, :] = np.inf                    # dropped: infinite location and target
+    dev = torch.from_numpy(D).cuda()
+    for k in (3, 40):
+        hh.pivot_add_examples(dev, k)
+    f, y = hh.pivot_examples()
+    f, y = f.cpu().numpy(), y.cpu().numpy()
+    t = 0
+    for k in (3, 40):
+        ov, _ = oracle.select_k(D, k)
+        for r in range(D.shape[0]):
+            x, m, s_ = mlp.features(mlp.row_sample(D[r]), D.shape[1], k)
+            target = (float(ov[r, k - 1]) - m) / s_
+            if not (np.all(np.isfinite(x)) and np.isfinite(target)):
+                continue
+            np.testing.assert_allclose(f[t], x, rtol=2e-4, atol=2e-5)
+            assert abs(y[t] - target) <= 1e-4 * max(1.0, abs(target))
+            t += 1
+    assert t == len(y) and t < 2 * D.shape[0]
+
+
+def test_train_is_deterministic_and_learns(torch, knn):
+    """knn_pivot_train from stored examples: the same seed gives the same
+    weights bit for bit, another seed other weights, and the trained network's
+    pinball loss is well below the initial one."""
+    from paper_1309_5478_amd import pivot_train
+    cfgs = [("gmm", 16384, 64, 1500), ("uniform", 16384, 32, 1501), ("normal", 8192, 128, 1502)]
+    ws = []
+    for seed in (7, 7, 8):
+        hh = knn.Handle(0, pivot_weights=None)
+        pivot_train.add_rows(hh, cfgs, rows_per_set=64)
+        hh.pivot_train(None, seed=seed, steps=0)
+        X, y = hh.pivot_examples()
+        _, loss0 = hh.pivot_grad(X.contiguous(), y.contiguous(), 0.99)
+        hh.pivot_train(None, seed=seed, steps=300)
+        _, loss1 = hh.pivot_grad(X.contiguous(), y.contiguous(), 0.99)
+        say(f"seed {seed}: {X.shape[0]} examples, pinball loss {float(loss0[0]):.4f} -> {float(loss1[0]):.4f}")
+        assert float(loss1[0]) < 0.5 * float(loss0[0])
+        ws.append(hh.pivot_get_weights())
+    assert np.array_equal(ws[0], ws[1])
+    assert not np.array_equal(ws[0], ws[2])
+
+
 def test_save_load_roundtrip(h, torch, knn):
     theta = rand_params(14)
     h.pivot_set_weights(theta)
@@ -138,8 +187,7 @@ def _trained_handle(knn, torch):
     say("no packaged pivot weights: training a small network")
     cfgs = [(kind, n, d, 1000 + i) for i, (kind, n, d) in enumerate(
         [(kd, n, d) for kd in pivot_train.KINDS for n in (16384, 65536) for d in (32, 256)])]
-    h, _ = pivot_train.train(out_path=None, steps=800, configs=cfgs, log=say)
-    return h
+    return pivot_train.train(out_path=None, steps=800, configs=cfgs, log=say)
 
 
 def test_learned_pivot_gain_over_plain(torch, knn):
