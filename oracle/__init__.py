@@ -16,6 +16,9 @@ It shares no code with the HIP path.
   pivot fill the output from the left in input order, the others fill it from
   the right end (so they appear in reverse input order).  numpy.
 * ``mlp``       -- FP64 forward/backward of the pivot network (see ``mlp.py``).
+* ``quant``     -- BF16 and OCP e4m3 conversions from the formats' definitions.
+* ``nth_select_k`` -- not a reference: the std::nth_element CPU baseline the
+  benchmark times beside the GPU selection (checked against ``select_k``).
 """
 from __future__ import annotations
 
@@ -28,17 +31,52 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "knn_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+_NTH_SRC = os.path.join(_HERE, "nth_baseline.cpp")
+_NTH_LIB = os.path.join(_HERE, "libnth.so")
 _lib = None
+_nth = None
 
 
 def build(force: bool = True) -> str:
-    """Compile the C oracle with gcc (FP contraction off)."""
+    """Compile the C oracle with gcc (FP contraction off), and the nth_element
+    CPU baseline with g++."""
     if force or not os.path.exists(_LIB):
         cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-pthread",
                _SRC, "-o", _LIB + ".tmp", "-lm"]
         subprocess.check_call(cmd)
         os.replace(_LIB + ".tmp", _LIB)
+    if force or not os.path.exists(_NTH_LIB):
+        cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-pthread", _NTH_SRC, "-o", _NTH_LIB + ".tmp"]
+        subprocess.check_call(cmd)
+        os.replace(_NTH_LIB + ".tmp", _NTH_LIB)
     return _LIB
+
+
+def _load_nth():
+    global _nth
+    if _nth is None:
+        if not os.path.exists(_NTH_LIB) or os.path.getmtime(_NTH_LIB) < os.path.getmtime(_NTH_SRC):
+            build()
+        lib = ctypes.CDLL(_NTH_LIB)
+        P = ctypes.c_void_p
+        lib.nth_select_k.argtypes = [P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, P, P,
+                                     ctypes.c_int32]
+        lib.nth_select_k.restype = ctypes.c_int
+        _nth = lib
+    return _nth
+
+
+def nth_select_k(D: np.ndarray, k: int, nthreads: int = 0):
+    """CPU comparison baseline (std::nth_element + sort of the first k per row;
+    not the oracle).  Returns (values float32 [r, k], indices int32 [r, k])."""
+    D = np.ascontiguousarray(D, dtype=np.float32)
+    rows, cols = D.shape
+    vals = np.empty((rows, k), np.float32)
+    idx = np.empty((rows, k), np.int32)
+    st = _load_nth().nth_select_k(_ptr(D), rows, cols, cols, k, _ptr(vals), _ptr(idx), nthreads)
+    if st != 0:
+        raise ValueError(f"nth_select_k failed with status {st}")
+    return vals, idx
 
 
 def bind(path: str):
@@ -52,6 +90,10 @@ def bind(path: str):
                                    ctypes.c_int32, P, P, P, ctypes.c_int32]
     lib.oracle_knn.restype = ctypes.c_int
     lib.oracle_default_threads.restype = ctypes.c_int
+    if hasattr(lib, "oracle_knn_metric"):
+        lib.oracle_knn_metric.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, P,
+                                          P, P, ctypes.c_int32, ctypes.c_int32]
+        lib.oracle_knn_metric.restype = ctypes.c_int
     return lib
 
 
@@ -91,8 +133,13 @@ def select_k(D: np.ndarray, k: int, rows=None, nthreads: int = 0, lib=None):
     return vals, idx
 
 
-def knn(Q: np.ndarray, C: np.ndarray, k: int, self_ids=None, nthreads: int = 0, lib=None):
-    """k nearest rows of C to each row of Q by FP64 direct squared distance.
+METRICS = {"sqeuclidean": 0, "cosine": 1, "pearson": 2}
+
+
+def knn(Q: np.ndarray, C: np.ndarray, k: int, self_ids=None, nthreads: int = 0, lib=None, metric="sqeuclidean"):
+    """k nearest rows of C to each row of Q by FP64 direct squared distance
+    (or, with metric, cosine distance 1 - cos, or Pearson distance 1 - r: the
+    cosine distance of the mean-centred vectors; NaN for a zero-norm vector).
     self_ids[i] (if given) is the corpus index excluded for query i.
     Returns (dist float64 [m, k], idx int32 [m, k]); missing entries (+inf, -1)."""
     Q = np.ascontiguousarray(Q, dtype=np.float32)
@@ -104,7 +151,8 @@ def knn(Q: np.ndarray, C: np.ndarray, k: int, self_ids=None, nthreads: int = 0, 
     sid = None if self_ids is None else np.ascontiguousarray(self_ids, dtype=np.int64)
     dist = np.empty((m, k), np.float64)
     idx = np.empty((m, k), np.int32)
-    st = (lib or _load()).oracle_knn(_ptr(Q), m, _ptr(C), n, d, k, _ptr(sid), _ptr(dist), _ptr(idx), nthreads)
+    st = (lib or _load()).oracle_knn_metric(_ptr(Q), m, _ptr(C), n, d, k, _ptr(sid), _ptr(dist), _ptr(idx),
+                                            nthreads, METRICS[metric])
     if st != 0:
         raise ValueError(f"oracle_knn failed with status {st}")
     return dist, idx

@@ -17,6 +17,12 @@
  *    are equal, all NaNs are equal to each other and above +inf, otherwise IEEE
  *    order.  Selected values are copied verbatim (bit for bit) from the input.
  *
+ *  - Cosine and Pearson distances (Methods, "Distance calculation": cosine
+ *    similarity of two vectors, and Pearson correlation as the cosine similarity
+ *    of the vectors minus their means), as the distance 1 - similarity, in FP64
+ *    from the FP32 inputs; a vector of zero norm (after centring) has no
+ *    direction, and its distances are NaN.
+ *
  *  - k-NN / k-NNG distances (Methods, "Distance calculation": squared Euclidean
  *    distance is what the neighbour comparison uses).  The oracle evaluates the
  *    direct difference form sum_t (q_t - c_t)^2 in FP64 from FP32 inputs (exactly
@@ -145,7 +151,45 @@ typedef struct {
     const int64_t *self_ids;
     double *out_dist; int32_t *out_idx;
     int tid, nthreads; int status;
+    int32_t metric;                  /* 0 squared Euclidean, 1 cosine, 2 Pearson */
+    const double *cmean, *cnorm;     /* per corpus vector (metrics 1 and 2) */
 } knn_job_t;
+
+/* Mean (Pearson only; 0 otherwise) and Euclidean norm of the centred vector, FP64. */
+static void centre_norm(const float *x, int32_t d, int32_t metric, double *mean, double *norm) {
+    double mu = 0.0;
+    if (metric == 2) {
+        for (int32_t t = 0; t < d; ++t) mu += (double)x[t];
+        mu /= (double)d;
+    }
+    double s = 0.0;
+    for (int32_t t = 0; t < d; ++t) {
+        double v = (double)x[t] - mu;
+        s += v * v;
+    }
+    *mean = mu;
+    *norm = sqrt(s);
+}
+
+/* Distance between query q and corpus vector y under the job's metric. */
+static double pair_distance(const knn_job_t *j, const float *q, double qmean, double qnorm, int64_t c) {
+    const float *y = j->C + c * (int64_t)j->d;
+    if (j->metric == 0) {
+        double s = 0.0;
+        for (int32_t t = 0; t < j->d; ++t) {
+            double diff = (double)q[t] - (double)y[t];
+            s += diff * diff;
+        }
+        return s;
+    }
+    /* cosine distance 1 - x.y / (|x| |y|) of the (centred) vectors; undefined
+     * (NaN) when either has zero norm */
+    const double ym = j->cmean[c], yn = j->cnorm[c];
+    if (qnorm == 0.0 || yn == 0.0) return NAN;
+    double dot = 0.0;
+    for (int32_t t = 0; t < j->d; ++t) dot += ((double)q[t] - qmean) * ((double)y[t] - ym);
+    return 1.0 - dot / (qnorm * yn);
+}
 
 static void *knn_worker(void *arg) {
     knn_job_t *j = (knn_job_t *)arg;
@@ -160,15 +204,11 @@ static void *knn_worker(void *arg) {
         const float *q = j->Q + i * (int64_t)j->d;
         int64_t self = j->self_ids ? j->self_ids[i] : -1;
         int64_t cnt = 0;
+        double qmean = 0.0, qnorm = 0.0;
+        if (j->metric != 0) centre_norm(q, j->d, j->metric, &qmean, &qnorm);
         for (int64_t c = 0; c < j->n; ++c) {
             if (c == self) continue;           /* k-NNG: exclude only the query itself */
-            const float *y = j->C + c * (int64_t)j->d;
-            double s = 0.0;
-            for (int32_t t = 0; t < j->d; ++t) {
-                double diff = (double)q[t] - (double)y[t];
-                s += diff * diff;
-            }
-            dist[cnt] = s;
+            dist[cnt] = pair_distance(j, q, qmean, qnorm, c);
             idx[cnt] = (int32_t)c;
             ++cnt;
         }
@@ -197,21 +237,37 @@ static void *knn_worker(void *arg) {
  * self_ids[i] is excluded for query i (k-NNG).  Positions beyond the number of
  * eligible corpus points are filled with (+inf, -1).
  * Returns 0 on success, 1 on invalid arguments, 2 on allocation failure. */
-int oracle_knn(const float *Q, int64_t m, const float *C, int64_t n, int32_t d, int32_t kout,
-               const int64_t *self_ids, double *out_dist, int32_t *out_idx, int32_t nthreads) {
-    if (!Q || !C || !out_dist || !out_idx || m < 0 || n < 1 || d < 1 || kout < 1 || n > INT32_MAX)
+int oracle_knn_metric(const float *Q, int64_t m, const float *C, int64_t n, int32_t d, int32_t kout,
+                      const int64_t *self_ids, double *out_dist, int32_t *out_idx, int32_t nthreads,
+                      int32_t metric) {
+    if (!Q || !C || !out_dist || !out_idx || m < 0 || n < 1 || d < 1 || kout < 1 || n > INT32_MAX ||
+        metric < 0 || metric > 2)
         return 1;
+    double *cmean = NULL, *cnorm = NULL;
+    if (metric != 0) {
+        cmean = (double *)malloc((size_t)n * sizeof(double));
+        cnorm = (double *)malloc((size_t)n * sizeof(double));
+        if (!cmean || !cnorm) { free(cmean); free(cnorm); return 2; }
+        for (int64_t c = 0; c < n; ++c) centre_norm(C + c * (int64_t)d, d, metric, &cmean[c], &cnorm[c]);
+    }
     int nt = resolve_threads(nthreads);
     if (nt > m) nt = m > 0 ? (int)m : 1;
     if (nt > 256) nt = 256;
     pthread_t th[256]; knn_job_t jobs[256];
     for (int t = 0; t < nt; ++t) {
-        jobs[t] = (knn_job_t){Q, m, C, n, d, kout, self_ids, out_dist, out_idx, t, nt, 0};
+        jobs[t] = (knn_job_t){Q, m, C, n, d, kout, self_ids, out_dist, out_idx, t, nt, 0, metric, cmean, cnorm};
         pthread_create(&th[t], NULL, knn_worker, &jobs[t]);
     }
     int status = 0;
     for (int t = 0; t < nt; ++t) { pthread_join(th[t], NULL); if (jobs[t].status) status = jobs[t].status; }
+    free(cmean); free(cnorm);
     return status;
+}
+
+/* Squared Euclidean k-NN (metric 0 of oracle_knn_metric). */
+int oracle_knn(const float *Q, int64_t m, const float *C, int64_t n, int32_t d, int32_t kout,
+               const int64_t *self_ids, double *out_dist, int32_t *out_idx, int32_t nthreads) {
+    return oracle_knn_metric(Q, m, C, n, d, kout, self_ids, out_dist, out_idx, nthreads, 0);
 }
 
 /* Number of worker threads a call with nthreads <= 0 uses. */

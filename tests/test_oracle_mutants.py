@@ -26,8 +26,12 @@ MUTANTS = {
     "corpus_stride": ("const float *y = j->C + c * (int64_t)j->d;", "const float *y = j->C + c;"),
     "values_not_verbatim": ("memcpy(&j->out_val[p * j->k + t], &row[idx[t]], sizeof(float));",
                             "j->out_val[p * j->k + t] = row[idx[t]] + 0.0f;"),
-    "dropped_last_term": ("for (int32_t t = 0; t < j->d; ++t) {\n                double diff",
-                          "for (int32_t t = 0; t + 1 < j->d; ++t) {\n                double diff"),
+    "dropped_last_term": ("for (int32_t t = 0; t < j->d; ++t) {\n            double diff",
+                          "for (int32_t t = 0; t + 1 < j->d; ++t) {\n            double diff"),
+    "pearson_not_centred": ("if (metric == 2) {", "if (metric == 3) {"),
+    "cosine_similarity_not_distance": ("return 1.0 - dot / (qnorm * yn);", "return dot / (qnorm * yn);"),
+    "cosine_norm_squared": ("*norm = sqrt(s);", "*norm = s;"),
+    "pearson_norm_uncentred": ("double v = (double)x[t] - mu;", "double v = (double)x[t];"),
 }
 
 
@@ -66,6 +70,15 @@ def _battery(lib):
     for r in range(6):
         if not np.allclose(d[r], ref[r, i[r]], rtol=1e-12, atol=0):
             failed.add("scipy")
+    # cosine and Pearson distances against scipy's cosine and correlation
+    Q = (rng.random((5, 9)) - 0.3).astype(np.float32)
+    C = (rng.random((30, 9)) - 0.3).astype(np.float32)
+    for metric, name in (("cosine", "cosine"), ("pearson", "correlation")):
+        d, i = oracle.knn(Q, C, 30, lib=lib, metric=metric)
+        ref = cdist(Q.astype(np.float64), C.astype(np.float64), name)
+        for r in range(5):
+            if not np.allclose(d[r], ref[r, i[r]], rtol=1e-10, atol=1e-14) or not (np.diff(d[r]) >= 0).all():
+                failed.add("scipy_" + metric)
     return failed
 
 
