@@ -219,3 +219,57 @@ def test_generators_are_counter_based():
     z = synth.normal_points(20000, 4, seed=1)
     assert abs(float(z.mean())) < 0.02 and abs(float(z.std()) - 1.0) < 0.02
     assert np.all((u * (1 << 24)) == np.floor(u * (1 << 24)))
+
+
+@pytest.mark.parametrize("k", [1, 5, 64, 300])
+def test_nth_baseline_matches_oracle(k):
+    """The nth_element CPU baseline selects the same entries, in the same
+    order, as the oracle's stable sort: ties, signed zeros and NaNs included."""
+    rng = np.random.default_rng(k)
+    D = rng.integers(0, 40, size=(30, 700)).astype(np.float32)
+    D[1, ::3] = -0.0
+    D[2, ::5] = np.nan
+    D[3] = rng.standard_normal(700).astype(np.float32)
+    ov, oi = oracle.select_k(D, k)
+    nv, ni = oracle.nth_select_k(D, k, nthreads=3)
+    assert np.array_equal(ni, oi)
+    assert np.array_equal(nv.view(np.uint32), ov.view(np.uint32))
+
+
+@pytest.mark.parametrize("metric,scipy_name", [("cosine", "cosine"), ("pearson", "correlation")])
+def test_oracle_cosine_pearson_match_scipy(metric, scipy_name):
+    rng = np.random.default_rng(11)
+    Q = rng.standard_normal((12, 33)).astype(np.float32)
+    C = rng.standard_normal((200, 33)).astype(np.float32)
+    d, i = oracle.knn(Q, C, 200, metric=metric)
+    ref = cdist(Q.astype(np.float64), C.astype(np.float64), scipy_name)
+    for r in range(12):
+        assert np.allclose(d[r], ref[r, i[r]], rtol=1e-12, atol=1e-15)
+        want = np.argsort(ref[r], kind="stable")
+        assert np.array_equal(i[r], want) or np.allclose(ref[r, i[r]], ref[r, want], rtol=1e-12)
+
+
+def test_oracle_cosine_hand_cases():
+    """x = (1, 0): y = (0, 1) is at distance 1, (1, 1) at 1 - 1/sqrt 2,
+    (-1, 0) at 2, (3, 0) at 0 (scale-free); a zero vector is at NaN, last."""
+    Q = np.array([[1, 0]], np.float32)
+    C = np.array([[0, 1], [1, 1], [-1, 0], [3, 0], [0, 0]], np.float32)
+    d, i = oracle.knn(Q, C, 5, metric="cosine")
+    assert i[0].tolist() == [3, 1, 0, 2, 4]
+    assert d[0, 0] == 0.0 and abs(d[0, 1] - (1 - 2 ** -0.5)) < 1e-15 and d[0, 2] == 1.0 and d[0, 3] == 2.0
+    assert np.isnan(d[0, 4])
+
+
+def test_oracle_pearson_invariances():
+    """Pearson distance ignores adding a constant to a vector and scaling it by
+    a positive factor; cosine distance ignores only the scaling."""
+    rng = np.random.default_rng(12)
+    Q = rng.integers(-20, 21, (4, 20)).astype(np.float32)
+    C = rng.integers(-20, 21, (60, 20)).astype(np.float32)
+    C2 = (C * np.float32(4.0) + np.float32(8.0)).astype(np.float32)   # exact in FP32 (small integers)
+    d1, i1 = oracle.knn(Q, C, 10, metric="pearson")
+    d2, i2 = oracle.knn(Q, C2, 10, metric="pearson")
+    assert np.array_equal(i1, i2) and np.allclose(d1, d2, rtol=1e-10, atol=1e-12)
+    e1, j1 = oracle.knn(Q, C, 10, metric="cosine")
+    e2, j2 = oracle.knn(Q, (C * np.float32(4.0)).astype(np.float32), 10, metric="cosine")
+    assert np.array_equal(j1, j2) and np.allclose(e1, e2, rtol=1e-12, atol=1e-15)
