@@ -33,7 +33,7 @@ def points(d):
     rows.append(np.zeros(d))
     special = rng.standard_normal(d)
     special[::7] = np.inf
-    special[3] = -np.inf
+    special[3 % d] = -np.inf                        # (d = 1: the only element)
     rows.append(special)
     nanrow = rng.standard_normal(d)
     nanrow[1::5] = np.nan
