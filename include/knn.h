@@ -103,12 +103,20 @@ typedef struct {
 /* search / graph / batch with FP32 products: treat every row as uncertified, so
  * that each row is re-run exactly from its materialised reduced-key row (tests). */
 #define KNN_FLAG_FORCE_RERUN 0x20
+/* knn_select_k: never split rows across workgroups (see knn_select_k). */
+#define KNN_FLAG_NO_SPLIT 0x40
+/* knn_select_k: split every row that is at least two minimal parts long,
+ * whatever the row count (tests). */
+#define KNN_FLAG_FORCE_SPLIT 0x80
 
 typedef struct {
-    int64_t rows;                 /* rows processed by the last call              */
+    int64_t rows;                 /* rows processed by the last call; with        */
+                                  /* split_parts > 1 the counters below sum (and  */
+                                  /* passes_max maximises) over the parts         */
     int64_t passes_total;         /* partition passes summed over rows            */
     int32_t passes_max;           /* most partition passes on one row             */
-    int32_t reserved0;
+    int32_t split_parts;          /* select_k: parts each row was cut into (1:    */
+                                  /* whole rows, one workgroup each)              */
     int64_t stream_passes_total;  /* full reads of an input row (select_k)        */
     int64_t spill_rows;           /* rows whose candidates left on-chip memory    */
     int64_t first_pass_survivors; /* keys kept by the first pass, summed          */
@@ -144,13 +152,23 @@ const char *knn_last_error(knn_handle_t h);
  * per row, ballot-based partition, K-versus-L recursion with a stack of segment
  * references).
  *
+ * Few long rows: the paper's GPU is only saturated with enough rows in flight
+ * (Results, Figure 8; Discussion).  When the rows are too few to give every
+ * resident workgroup one, each row is cut into parts of at least
+ * max(4096, 32 k) columns (a power of two of them), every part's k smallest
+ * keys are selected by its own workgroup, and the parts' lists are merged by
+ * key-list selections; the result is the same, bit for bit.  The flags
+ * KNN_FLAG_NO_SPLIT / KNN_FLAG_FORCE_SPLIT turn this off / force it.
+ *
  *   dist     rows x cols FP32, row stride ld (>= cols)            [in, device]
  *   k        1 <= k <= min(cols, 1024)
  *   out_val  rows x k FP32: the selected entries, bit-for-bit copies [out]
- *   out_idx  rows x k int32: their column indices                  [out]
- *   opt      NULL for defaults; only `pivot` is used
- * Errors: INVALID_VALUE for null pointers, rows < 0, cols < 1, ld < cols,
- * k < 1 or k > cols; UNSUPPORTED for k > 1024 or cols > INT32_MAX.
+ *   out_idx  rows x k int32: their column indices, or NULL for values only
+ *            (Results: the selection measured on values alone)     [out]
+ *   opt      NULL for defaults; `pivot` and the split flags are used
+ * Errors: INVALID_VALUE for null dist / out_val, rows < 0, cols < 1, ld < cols,
+ * k < 1, k > cols, or both split flags; UNSUPPORTED for k > 1024 or
+ * cols > INT32_MAX.
  */
 knn_status_t knn_select_k(knn_handle_t h, const float *dist, int64_t rows, int64_t cols,
                           int64_t ld, int32_t k, float *out_val, int32_t *out_idx,

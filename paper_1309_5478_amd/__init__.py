@@ -11,7 +11,8 @@ import ctypes
 
 from . import _abi
 from ._abi import (PIVOT_LEARNED, PIVOT_PLAIN, PIVOT_SAMPLE, PREC_BF16, PREC_FP32,  # noqa: F401
-                   PREC_FP8_E4M3, FLAG_FORCE_FALLBACK, FLAG_UNFUSED, FLAG_TIMING, FLAG_NO_GRAPH, FLAG_AUTOTUNE, FLAG_FORCE_RERUN, Job, Options,
+                   PREC_FP8_E4M3, FLAG_FORCE_FALLBACK, FLAG_UNFUSED, FLAG_TIMING, FLAG_NO_GRAPH, FLAG_AUTOTUNE, FLAG_FORCE_RERUN, FLAG_NO_SPLIT,
+                   FLAG_FORCE_SPLIT, Job, Options,
                    Stats)
 
 _PIVOTS = {"plain": PIVOT_PLAIN, "sample": PIVOT_SAMPLE, "learned": PIVOT_LEARNED}
@@ -83,19 +84,21 @@ class Handle:
         self._check(self.lib.knn_get_stats(self.h, ctypes.byref(s)))
         return s.as_dict()
 
-    def select_k(self, dist, k: int, pivot="sample"):
+    def select_k(self, dist, k: int, pivot="sample", flags=0, indices=True):
         """k smallest entries per row of a 2-D FP32 CUDA tensor (row stride may
-        exceed the width).  Returns (values [rows, k] f32, indices [rows, k] i32)."""
+        exceed the width).  Returns (values [rows, k] f32, indices [rows, k] i32),
+        or (values, None) with indices=False (values only)."""
         torch = _torch()
         if dist.dim() != 2 or dist.dtype != torch.float32 or not dist.is_cuda or dist.stride(1) != 1:
             raise ValueError("dist must be a 2-D float32 device tensor with unit column stride")
         rows, cols = dist.shape
         vals = torch.empty((rows, k), dtype=torch.float32, device=dist.device)
-        idx = torch.empty((rows, k), dtype=torch.int32, device=dist.device)
-        o = self._opts(pivot)
+        idx = torch.empty((rows, k), dtype=torch.int32, device=dist.device) if indices else None
+        o = self._opts(pivot, flags=flags)
         self._check(self.lib.knn_select_k(self.h, ctypes.c_void_p(dist.data_ptr()), rows, cols,
                                           max(dist.stride(0), cols), k, ctypes.c_void_p(vals.data_ptr()),
-                                          ctypes.c_void_p(idx.data_ptr()), self._stream(), ctypes.byref(o)))
+                                          ctypes.c_void_p(idx.data_ptr() if idx is not None else 0),
+                                          self._stream(), ctypes.byref(o)))
         return vals, idx
 
     def partition(self, x, piv_val, piv_idx):

@@ -21,6 +21,8 @@ FLAG_TIMING = 0x4
 FLAG_NO_GRAPH = 0x8
 FLAG_AUTOTUNE = 0x10
 FLAG_FORCE_RERUN = 0x20
+FLAG_NO_SPLIT = 0x40
+FLAG_FORCE_SPLIT = 0x80
 PIVOT_NPARAM = 4801
 
 
@@ -37,7 +39,7 @@ class Job(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("rows", ctypes.c_int64), ("passes_total", ctypes.c_int64),
-                ("passes_max", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("passes_max", ctypes.c_int32), ("split_parts", ctypes.c_int32),
                 ("stream_passes_total", ctypes.c_int64), ("spill_rows", ctypes.c_int64),
                 ("first_pass_survivors", ctypes.c_int64), ("fallback_rows", ctypes.c_int64),
                 ("candidates_total", ctypes.c_int64), ("phase_cycles", ctypes.c_int64 * 4),
@@ -47,7 +49,7 @@ class Stats(ctypes.Structure):
 
     def as_dict(self):
         d = {name: int(getattr(self, name)) for name, _ in self._fields_
-             if name not in ("reserved0", "phase_cycles", "product_ms", "product_flops")}
+             if name not in ("phase_cycles", "product_ms", "product_flops")}
         d["product_ms"] = float(self.product_ms)
         d["product_flops"] = float(self.product_flops)
         d["phase_cycles"] = [int(x) for x in self.phase_cycles]

@@ -152,6 +152,7 @@ static knn_status_t begin_stats(knn_handle_t h, hipStream_t stream) {
     h->host_product_ms = 0;
     h->host_product_flops = 0;
     h->host_product_launches = 0;
+    h->last_split_parts = 1;
     return KNN_SUCCESS;
 }
 
@@ -168,17 +169,24 @@ knn_status_t knn_select_k(knn_handle_t h, const float *dist, int64_t rows, int64
     int mode = opt ? opt->pivot : kPivotSample;
     if (mode < kPivotPlain || mode > kPivotLearned) return fail(h, KNN_ERROR_INVALID_VALUE, "knn_select_k: bad pivot mode");
     if (rows == 0) return KNN_SUCCESS;
-    if (!dist || !out_val || !out_idx) return fail(h, KNN_ERROR_INVALID_VALUE, "knn_select_k: null pointer");
+    if (!dist || !out_val) return fail(h, KNN_ERROR_INVALID_VALUE, "knn_select_k: null pointer");
+    const int flags = opt ? opt->flags : 0;
+    if ((flags & KNN_FLAG_NO_SPLIT) && (flags & KNN_FLAG_FORCE_SPLIT))
+        return fail(h, KNN_ERROR_INVALID_VALUE, "knn_select_k: NO_SPLIT and FORCE_SPLIT together");
     hipStream_t stream = static_cast<hipStream_t>(stream_);
     hipSetDevice(h->device);
     if (mode == kPivotLearned && !h->has_net) mode = kPivotSample;  // no pivot network loaded: sample rule
     int cap = select_cap_for_k((uint32_t)k);
-    int grid = select_grid(cap, rows, h->num_cu);
+    SplitPlan sp{1, 1, (uint32_t)cols, 0};
+    if (!(flags & KNN_FLAG_NO_SPLIT))
+        sp = select_split_plan(rows, (uint32_t)cols, (uint32_t)k, h->num_cu, (flags & KNN_FLAG_FORCE_SPLIT) != 0);
+    int grid = sp.parts > 1 ? sp.grid : select_grid(cap, rows, h->num_cu);
     void *ws = nullptr;
-    size_t need = select_ws_bytes(cap, (uint32_t)cols, grid);
+    size_t need = sp.parts > 1 ? select_split_ws_bytes(sp, rows, (uint32_t)k) : select_ws_bytes(cap, (uint32_t)cols, grid);
     knn_status_t st = ensure_ws(h, need < 256 ? 256 : need, stream, &ws);
     if (st != KNN_SUCCESS) return st;
     if ((st = begin_stats(h, stream)) != KNN_SUCCESS) return st;
+    h->last_split_parts = sp.parts;
     SelectArgs a{};
     a.dist = dist;
     a.rows = rows;
@@ -190,7 +198,7 @@ knn_status_t knn_select_k(knn_handle_t h, const float *dist, int64_t rows, int64
     a.net = mode == kPivotLearned ? h->net_bf16 : nullptr;
     a.mode = mode;
     a.stats = h->stats_dev;
-    hipError_t e = launch_select(a, cap, grid, ws, stream);
+    hipError_t e = sp.parts > 1 ? launch_select_split(a, sp, ws, h->num_cu, stream) : launch_select(a, cap, grid, ws, stream);
     if (e != hipSuccess) return hip_fail(h, e, "select kernel launch");
     return KNN_SUCCESS;
 }
@@ -351,9 +359,11 @@ knn_status_t knn_get_stats(knn_handle_t h, knn_stats_t *out) {
         if (s[kStatErrors] != 0)
             return fail(h, KNN_ERROR_DEVICE, "a kernel reported an internal error on " + std::to_string(s[kStatErrors]) + " rows");
         knn_stats_t t{};
-        t.rows = (int64_t)s[kStatRows];
+        // a split row's parts count one row each
+        t.rows = (int64_t)s[kStatRows] / (h->last_split_parts > 1 ? h->last_split_parts : 1);
         t.passes_total = (int64_t)s[kStatPasses];
         t.passes_max = (int32_t)s[kStatPassesMax];
+        t.split_parts = h->last_split_parts;
         t.stream_passes_total = (int64_t)s[kStatStreamPasses];
         t.spill_rows = (int64_t)s[kStatSpillRows];
         t.first_pass_survivors = (int64_t)s[kStatFirstSurvivors];

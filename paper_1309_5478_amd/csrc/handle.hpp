@@ -23,6 +23,7 @@ struct knn_handle_s {
     int64_t host_rows = 0, host_fallback = 0, host_rerun = 0;  // host-side counters of the last call
     double host_product_ms = 0, host_product_flops = 0;
     int64_t host_product_launches = 0;
+    int32_t last_split_parts = 1;              // parts per row of the last knn_select_k
     uint32_t *pinned = nullptr;                 // one pinned word for device-to-host counts
     std::string err;
     // pivot network: FP32 master weights, their BF16-rounded values (as FP32 for

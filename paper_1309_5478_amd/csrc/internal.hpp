@@ -64,6 +64,21 @@ struct SelectArgs {
     const uint32_t *row_seg;
     // row counter for dynamic row claiming (set by launch_select), or null
     unsigned long long *next_row;
+    // Rows split into parts (split > 1, dense rows only): launch row r is part
+    // r % split of matrix row r / split, columns [p cols, min((p + 1) cols,
+    // row_cols)); its min(k, part length) smallest keys, with the part's column
+    // offset added to their indices, go to out_keys + r k and the rest of the
+    // k slots are padded with the largest key.
+    uint32_t split;
+    uint32_t row_cols;
+    // When set, every row's selected keys go here (rows x k, ascending) instead
+    // of out_val / out_idx.
+    uint64_t *out_keys;
+    // Key-list rows whose keys index the columns of a given matrix: values of the
+    // zero and NaN classes are copied from src + r * src_ld + index, so that they
+    // keep their bits (sign of zero, NaN payload).
+    const float *src;
+    int64_t src_ld;
 };
 
 // Largest k a selection call supports.
@@ -85,6 +100,25 @@ constexpr int kSelectKeysCap = 4096;
 // launch's row counter.
 hipError_t launch_select_keys(const SelectArgs &a, void *counter, int64_t rows_grid_limit, int num_cu,
                               hipStream_t stream);
+
+// ---- rows split across workgroups -----------------------------------------------
+// Few long rows leave most of the device idle with one workgroup per row.  Each
+// row is then cut into `parts` parts (a power of two) selected independently,
+// and the parts' key lists are merged by key-list selections, up to `group`
+// lists of k keys per merged row and level (a power of two with group k <=
+// kSelectKeysCap), until one list per row remains: exact, since keys form a
+// total order and the k smallest of a row lie among the k smallest of its parts.
+struct SplitPlan {
+    uint32_t parts, group, chunk;  // chunk: columns per part (a multiple of 4)
+    int grid;                      // workgroups of the part selection
+};
+// parts = 1 when splitting is not worth it; `force` splits whenever the row is
+// at least two minimal parts long.
+SplitPlan select_split_plan(int64_t rows, uint32_t cols, uint32_t k, int num_cu, bool force);
+size_t select_split_ws_bytes(const SplitPlan &sp, int64_t rows, uint32_t k);
+// a: the whole call as for launch_select (dist, rows, cols, ld, k, outputs,
+// mode, net, stats; out_idx may be null).
+hipError_t launch_select_split(const SelectArgs &a, const SplitPlan &sp, void *ws, int num_cu, hipStream_t stream);
 
 // ---- one partition pass, one wavefront per row ------------------------------
 hipError_t launch_partition(const float *in, int64_t rows, uint32_t cols, int64_t ld,

@@ -441,10 +441,18 @@ __global__ __launch_bounds__(kSelThreads, KEYS ? 1 : (CAP == kSelectCap ? 5 : (C
         const float *dist = a.dist;
         const uint64_t *keys = a.keys;
         const uint32_t *key_cnt = a.key_cnt;
-        int64_t ld = a.ld, lr = r;
-        uint32_t N = a.cols, k = a.k;
+        int64_t ld = a.ld, lr = r, orow = r;
+        uint32_t N = a.cols, k = a.k, kout = a.k, col_off = 0;
         float *out_val = a.out_val;
         int32_t *out_idx = a.out_idx;
+        if (!KEYS && a.split > 1) {
+            // part p of matrix row r / split
+            lr = r / a.split;
+            col_off = (uint32_t)(r - lr * a.split) * a.cols;
+            const uint32_t rest = a.row_cols - col_off;
+            N = rest < a.cols ? rest : a.cols;
+            k = k < N ? k : N;
+        }
         if (a.segs) {
             const SelectSeg sg = uniform_load(a.segs + __builtin_amdgcn_readfirstlane(a.row_seg[r]));
             dist = sg.dist;
@@ -452,13 +460,15 @@ __global__ __launch_bounds__(kSelThreads, KEYS ? 1 : (CAP == kSelectCap ? 5 : (C
             key_cnt = sg.key_cnt;
             ld = sg.ld;
             lr = r - sg.row0;
+            orow = lr;
             N = sg.cols;
             k = sg.k;
+            kout = k;
             out_val = sg.out_val;
             out_idx = sg.out_idx;
         }
-        const float *row = dist + lr * ld;
-        const bool vec = ((reinterpret_cast<uintptr_t>(dist) & 15u) == 0) && ((ld & 3) == 0);
+        const float *row = dist + lr * ld + col_off;
+        const bool vec = ((reinterpret_cast<uintptr_t>(row) & 15u) == 0) && ((ld & 3) == 0);
         uint32_t nstack = 0, agg = 0, passes = 0, stream_passes = 0, spill = 0, first = 0;
         uint32_t wide_lo = 0, wide_hi = 0;  // streamed range of buffer 0 still in the streaming layout
         long long cyc_sample = 0, cyc_stream = 0;
@@ -466,7 +476,7 @@ __global__ __launch_bounds__(kSelThreads, KEYS ? 1 : (CAP == kSelectCap ? 5 : (C
 
         if (KEYS) {
             // key-list row (at most CAP keys, at least k of them)
-            const uint32_t c = key_cnt[lr];
+            const uint32_t c = key_cnt ? key_cnt[lr] : N;
             const uint32_t n = c < N ? c : N;
             const uint64_t *src = keys + lr * ld;
             for (uint32_t p = tid; p < n; p += kSelThreads) sm.buf[0][p] = src[p];
@@ -677,17 +687,29 @@ __global__ __launch_bounds__(kSelThreads, KEYS ? 1 : (CAP == kSelectCap ? 5 : (C
         }
         // (agg == k on every normal exit)
         auto emit = [&](uint32_t t, uint64_t key) {
+            const int64_t o_at = orow * (int64_t)kout + t;
+            if (a.out_keys) {
+                // kKeyMax (internal-error path) stays the largest key
+                a.out_keys[o_at] = key == kKeyMax ? kKeyMax : key + col_off;
+                return;
+            }
             uint32_t idx = key_idx(key), o = key_ord(key);
             float v;
             if (key == kKeyMax) {  // only on the reported internal-error path
                 v = __uint_as_float(0x7fc00000u);
                 idx = 0xFFFFFFFFu;
+            } else if (o == kOrdZero || o == kOrdNaN) {
+                // the key holds the class, the input its bits
+                v = !KEYS ? row[idx] : (a.src ? a.src[lr * a.src_ld + idx] : ord_to_float(o));
             } else {
-                v = (!KEYS && (o == kOrdZero || o == kOrdNaN)) ? row[idx] : ord_to_float(o);
+                v = ord_to_float(o);
             }
-            out_val[lr * k + t] = v;
-            out_idx[lr * k + t] = (int32_t)idx;
+            out_val[o_at] = v;
+            if (out_idx) out_idx[o_at] = (int32_t)(idx + col_off);
         };
+        // a part shorter than k: its missing slots hold the largest key
+        if (!KEYS && a.out_keys)
+            for (uint32_t t = k + tid; t < kout; t += kSelThreads) a.out_keys[orow * (int64_t)kout + t] = kKeyMax;
         if (direct) {
             // no kept segments: the active segment [0, se) of buffer sb (its
             // tail possibly in the workspace) holds every key below its upper
@@ -902,6 +924,101 @@ hipError_t launch_select_keys(const SelectArgs &args, void *counter, int64_t row
     hipLaunchKernelGGL((select_rows_kernel<kSelectKeysCap, true>), dim3((unsigned)g), dim3(kSelThreads), 0, stream, a,
                        (uint64_t *)nullptr, (uint64_t)0);
     return hipGetLastError();
+}
+
+// ---- rows split across workgroups -------------------------------------------
+// A part is worth its own workgroup once it is long against the work that does
+// not scale with its length (the pivot sample, the final sort of about k keys
+// and the merge of its k keys): at least 4096 columns and 32 k.
+static uint64_t split_min_chunk(uint32_t k) { return k * 32ull > 4096ull ? k * 32ull : 4096ull; }
+
+SplitPlan select_split_plan(int64_t rows, uint32_t cols, uint32_t k, int num_cu, bool force) {
+    SplitPlan sp{1, 1, cols, 0};
+    const int64_t resident = (int64_t)blocks_per_cu<kSelectCap>() * num_cu;
+    // enough rows to keep every resident workgroup busy: nothing to gain
+    if (rows < 1 || (!force && rows * 2 > resident)) return sp;
+    uint32_t group = 2;
+    while (2ull * group * k <= (uint64_t)kSelectKeysCap) group *= 2;
+    const uint64_t min_chunk = split_min_chunk(k);
+    // two workgroups' worth of parts per resident slot, so that dynamic row
+    // claiming evens out the parts' costs
+    const int64_t want = force ? INT64_MAX : 2 * resident;
+    uint32_t parts = 1;
+    while (parts < 4096u && rows * (int64_t)parts < want && (uint64_t)cols >= 2ull * parts * min_chunk) parts *= 2;
+    for (; parts > 1; parts /= 2) {
+        // every part keeps at least one column (the last one may be short)
+        const uint64_t chunk = (((uint64_t)cols + parts - 1) / parts + 3) / 4 * 4;
+        if ((uint64_t)(parts - 1) * chunk < cols) {
+            sp.chunk = (uint32_t)chunk;
+            break;
+        }
+    }
+    if (parts < 2) return sp;
+    sp.parts = parts;
+    sp.group = group;
+    sp.grid = select_grid(kSelectCap, rows * parts, num_cu);
+    return sp;
+}
+
+// Workspace of a split call: the part selection's (header with its row counter,
+// overflow buffers), a 256-byte block with the merges' row counter, then two
+// key arrays: the parts' lists and the first merge level's.
+static size_t split_keys_a(const SplitPlan &sp, int64_t rows, uint32_t k) { return (size_t)rows * sp.parts * k; }
+static size_t split_keys_b(const SplitPlan &sp, int64_t rows, uint32_t k) {
+    const uint32_t g = sp.group < sp.parts ? sp.group : sp.parts;
+    return (size_t)rows * (sp.parts / g) * k;
+}
+
+size_t select_split_ws_bytes(const SplitPlan &sp, int64_t rows, uint32_t k) {
+    const size_t sel = (select_ws_bytes(kSelectCap, sp.chunk, sp.grid) + 255) / 256 * 256;
+    return sel + 256 + (split_keys_a(sp, rows, k) + split_keys_b(sp, rows, k)) * sizeof(uint64_t);
+}
+
+hipError_t launch_select_split(const SelectArgs &a, const SplitPlan &sp, void *ws, int num_cu, hipStream_t stream) {
+    if (!ws || sp.parts < 2 || a.k > (uint32_t)kSelectMaxK || (uint64_t)sp.group * a.k > (uint64_t)kSelectKeysCap)
+        return hipErrorInvalidValue;
+    char *w = static_cast<char *>(ws);
+    const size_t sel = (select_ws_bytes(kSelectCap, sp.chunk, sp.grid) + 255) / 256 * 256;
+    void *counter = w + sel;
+    uint64_t *ka = reinterpret_cast<uint64_t *>(w + sel + 256);
+    uint64_t *kb = ka + split_keys_a(sp, a.rows, a.k);
+    // 1. every part's k smallest keys, global column indices
+    SelectArgs pa = a;
+    pa.rows = a.rows * sp.parts;
+    pa.cols = sp.chunk;
+    pa.row_cols = a.cols;
+    pa.split = sp.parts;
+    pa.out_keys = ka;
+    pa.out_val = nullptr;
+    pa.out_idx = nullptr;
+    hipError_t e = launch_select(pa, kSelectCap, sp.grid, ws, stream);
+    if (e != hipSuccess) return e;
+    // 2. merge levels: `group` lists of k keys per merged row
+    uint64_t *in = ka, *out = kb;
+    for (uint32_t cur = sp.parts; cur > 1;) {
+        const uint32_t g = sp.group < cur ? sp.group : cur, next = cur / g;
+        SelectArgs m{};
+        m.keys = in;
+        m.rows = a.rows * next;
+        m.cols = g * a.k;
+        m.ld = (int64_t)g * a.k;
+        m.k = a.k;
+        m.mode = kPivotSample;
+        if (next == 1) {
+            m.out_val = a.out_val;
+            m.out_idx = a.out_idx;
+            m.src = a.dist;
+            m.src_ld = a.ld;
+        } else {
+            m.out_keys = out;
+        }
+        if ((e = launch_select_keys(m, counter, m.rows, num_cu, stream)) != hipSuccess) return e;
+        uint64_t *t = in;
+        in = out;
+        out = t;
+        cur = next;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_partition(const float *in, int64_t rows, uint32_t cols, int64_t ld, const float *piv_val,

@@ -28,7 +28,7 @@ C2 = 0xD1B54A32D192ED03
 # Seeds per workload (evaluation seeds; the pivot-network training draws from
 # seeds >= 1000 so that training rows never coincide with evaluation rows).
 SEEDS = {"knng_small": 1, "select": 2, "knng_fused": 3, "lowprec": 4, "batch": 5,
-         "train_base": 1000}
+         "sweep": 6, "metric": 7, "train_base": 1000}
 
 # Stream ids (arbitrary distinct constants).
 S_UNIFORM = 11
