@@ -175,6 +175,25 @@ knn_status_t knn_select_k(knn_handle_t h, const float *dist, int64_t rows, int64
                           void *stream, const knn_options_t *opt);
 
 /*
+ * knn_select_k_noalloc -- knn_select_k for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  Same arguments, checks and results as knn_select_k
+ * (values only with out_idx NULL), but it allocates nothing: its workspace is
+ * a static 64 MiB device array that the library holds on every device it runs
+ * on until the process ends.  Rows are never split across workgroups; rows
+ * longer than 8192 columns run with fewer workgroups at once so that their
+ * overflow buffers (2 (cols - 1024) keys of 8 bytes per workgroup) fit the
+ * array.  Every call on one device shares that device's array: calls that
+ * overlap in time on one device (on different streams, or from different
+ * handles or threads) race and give undefined results; order them.
+ * Errors: as knn_select_k, plus UNSUPPORTED for cols above 4195312 (one
+ * workgroup's overflow buffers would not fit) or a device ordinal >= 64.
+ */
+knn_status_t knn_select_k_noalloc(knn_handle_t h, const float *dist, int64_t rows, int64_t cols,
+                                  int64_t ld, int32_t k, float *out_val, int32_t *out_idx,
+                                  void *stream, const knn_options_t *opt);
+
+/*
  * knn_partition -- one partition pass per row, as the paper describes it for one
  * warp per row (Methods, "GPU-based quick multi-select", and Figures 1-3): the
  * row is read in 64-element segments, a wavefront ballot on "key below pivot"

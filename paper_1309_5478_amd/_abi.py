@@ -67,6 +67,7 @@ PROTOTYPES = {
     "knn_status_string": (ctypes.c_char_p, [_ST]),
     "knn_last_error": (ctypes.c_char_p, [_P]),
     "knn_select_k": (_ST, [_P, _P, _I64, _I64, _I64, _I32, _P, _P, _P, ctypes.POINTER(Options)]),
+    "knn_select_k_noalloc": (_ST, [_P, _P, _I64, _I64, _I64, _I32, _P, _P, _P, ctypes.POINTER(Options)]),
     "knn_partition": (_ST, [_P, _P, _I64, _I64, _I64, _P, _P, _P, _P, _P, _P]),
     "knn_search": (_ST, [_P, _P, _I64, _P, _I64, _I32, _I32, _P, _P, _P, ctypes.POINTER(Options)]),
     "knn_graph": (_ST, [_P, _P, _I64, _I32, _I32, _P, _P, _P, ctypes.POINTER(Options)]),

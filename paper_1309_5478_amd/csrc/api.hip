@@ -16,6 +16,35 @@ using namespace knn;
 
 static thread_local std::string g_err;  // errors with no handle
 
+namespace knn {
+// Workspace of knn_select_k_noalloc: one array per device, reserved when the
+// library's code object is loaded there and held until the process ends.  In
+// host code `scratch` only names the symbol; its device address on each device
+// comes from hipGetSymbolAddress, looked up once per device (knn_create).
+constexpr size_t kScratchBytes = 64ull << 20;
+// longest rows whose overflow buffers (2 (cols - 1024) keys) fit one workgroup
+constexpr int64_t kScratchMaxCols = 1024 + (int64_t)((kScratchBytes - 256) / 16);
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+// The device address of `scratch` on the current device `device`.
+static hipError_t scratch_address(int device, void **out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipSuccess;  // none: the entry point reports it
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+}  // namespace knn
+
 static knn_status_t fail(knn_handle_t h, knn_status_t s, const std::string &msg) {
     if (h) h->err = msg;
     else g_err = msg;
@@ -109,8 +138,11 @@ knn_status_t knn_create(knn_handle_t *out, int device) {
     if (arch.rfind("gfx950", 0) != 0)
         return fail(nullptr, KNN_ERROR_UNSUPPORTED, "knn_create: device is " + arch + ", libknn is built for gfx950 only");
     if ((e = hipSetDevice(device)) != hipSuccess) return hip_fail(nullptr, e, "hipSetDevice");
+    void *scr = nullptr;
+    if ((e = scratch_address(device, &scr)) != hipSuccess) return hip_fail(nullptr, e, "hipGetSymbolAddress(scratch)");
     knn_handle_t h = new knn_handle_s();
     h->device = device;
+    h->scratch = scr;
     h->num_cu = prop.multiProcessorCount;
     h->arch = arch;
     if ((e = hipMalloc(&h->stats_dev, kStatCount * sizeof(unsigned long long))) != hipSuccess) {
@@ -156,20 +188,30 @@ static knn_status_t begin_stats(knn_handle_t h, hipStream_t stream) {
     return KNN_SUCCESS;
 }
 
+// Argument checks shared by knn_select_k and knn_select_k_noalloc.
+static knn_status_t check_select(knn_handle_t h, const char *fn, const float *dist, int64_t rows, int64_t cols,
+                                 int64_t ld, int32_t k, const float *out_val, const knn_options_t *opt) {
+    const std::string f(fn);
+    if (!h) return fail(nullptr, KNN_ERROR_INVALID_VALUE, f + ": handle is null");
+    if (rows < 0) return fail(h, KNN_ERROR_INVALID_VALUE, f + ": rows < 0");
+    if (cols < 1) return fail(h, KNN_ERROR_INVALID_VALUE, f + ": cols < 1");
+    if (ld < cols) return fail(h, KNN_ERROR_INVALID_VALUE, f + ": ld < cols");
+    if (k < 1) return fail(h, KNN_ERROR_INVALID_VALUE, f + ": k < 1");
+    if (k > cols) return fail(h, KNN_ERROR_INVALID_VALUE, f + ": k > cols");
+    if (cols > INT32_MAX) return fail(h, KNN_ERROR_UNSUPPORTED, f + ": cols > INT32_MAX");
+    if (k > kSelectMaxK) return fail(h, KNN_ERROR_UNSUPPORTED, f + ": k > 1024");
+    const int mode = opt ? opt->pivot : kPivotSample;
+    if (mode < kPivotPlain || mode > kPivotLearned) return fail(h, KNN_ERROR_INVALID_VALUE, f + ": bad pivot mode");
+    if (rows > 0 && (!dist || !out_val)) return fail(h, KNN_ERROR_INVALID_VALUE, f + ": null pointer");
+    return KNN_SUCCESS;
+}
+
 knn_status_t knn_select_k(knn_handle_t h, const float *dist, int64_t rows, int64_t cols, int64_t ld, int32_t k,
                           float *out_val, int32_t *out_idx, void *stream_, const knn_options_t *opt) {
-    if (!h) return fail(nullptr, KNN_ERROR_INVALID_VALUE, "knn_select_k: handle is null");
-    if (rows < 0) return fail(h, KNN_ERROR_INVALID_VALUE, "knn_select_k: rows < 0");
-    if (cols < 1) return fail(h, KNN_ERROR_INVALID_VALUE, "knn_select_k: cols < 1");
-    if (ld < cols) return fail(h, KNN_ERROR_INVALID_VALUE, "knn_select_k: ld < cols");
-    if (k < 1) return fail(h, KNN_ERROR_INVALID_VALUE, "knn_select_k: k < 1");
-    if (k > cols) return fail(h, KNN_ERROR_INVALID_VALUE, "knn_select_k: k > cols");
-    if (cols > INT32_MAX) return fail(h, KNN_ERROR_UNSUPPORTED, "knn_select_k: cols > INT32_MAX");
-    if (k > kSelectMaxK) return fail(h, KNN_ERROR_UNSUPPORTED, "knn_select_k: k > 1024");
-    int mode = opt ? opt->pivot : kPivotSample;
-    if (mode < kPivotPlain || mode > kPivotLearned) return fail(h, KNN_ERROR_INVALID_VALUE, "knn_select_k: bad pivot mode");
+    knn_status_t cs = check_select(h, "knn_select_k", dist, rows, cols, ld, k, out_val, opt);
+    if (cs != KNN_SUCCESS) return cs;
     if (rows == 0) return KNN_SUCCESS;
-    if (!dist || !out_val) return fail(h, KNN_ERROR_INVALID_VALUE, "knn_select_k: null pointer");
+    int mode = opt ? opt->pivot : kPivotSample;
     const int flags = opt ? opt->flags : 0;
     if ((flags & KNN_FLAG_NO_SPLIT) && (flags & KNN_FLAG_FORCE_SPLIT))
         return fail(h, KNN_ERROR_INVALID_VALUE, "knn_select_k: NO_SPLIT and FORCE_SPLIT together");
@@ -199,6 +241,49 @@ knn_status_t knn_select_k(knn_handle_t h, const float *dist, int64_t rows, int64
     a.mode = mode;
     a.stats = h->stats_dev;
     hipError_t e = sp.parts > 1 ? launch_select_split(a, sp, ws, h->num_cu, stream) : launch_select(a, cap, grid, ws, stream);
+    if (e != hipSuccess) return hip_fail(h, e, "select kernel launch");
+    return KNN_SUCCESS;
+}
+
+knn_status_t knn_select_k_noalloc(knn_handle_t h, const float *dist, int64_t rows, int64_t cols, int64_t ld,
+                                  int32_t k, float *out_val, int32_t *out_idx, void *stream_,
+                                  const knn_options_t *opt) {
+    knn_status_t cs = check_select(h, "knn_select_k_noalloc", dist, rows, cols, ld, k, out_val, opt);
+    if (cs != KNN_SUCCESS) return cs;
+    if (!h->scratch) return fail(h, KNN_ERROR_UNSUPPORTED, "knn_select_k_noalloc: no scratch array on this device");
+    const int cap = select_cap_for_k((uint32_t)k);
+    // workgroups whose overflow buffers fit the array (all of them unless rows
+    // are long: each needs 2 (cols - 1024) keys)
+    const size_t one = select_ws_bytes(cap, (uint32_t)cols, 1), hdr = select_ws_bytes(cap, (uint32_t)cols, 0);
+    if (one > kScratchBytes)
+        return fail(h, KNN_ERROR_UNSUPPORTED,
+                    "knn_select_k_noalloc: rows of " + std::to_string(cols) + " columns need " + std::to_string(one) +
+                        " bytes of scratch per workgroup, above the " + std::to_string(kScratchBytes) +
+                        "-byte array (at most " + std::to_string(kScratchMaxCols) + " columns)");
+    if (rows == 0) return KNN_SUCCESS;
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    hipSetDevice(h->device);
+    int grid = select_grid(cap, rows, h->num_cu);
+    if (one > hdr) {
+        const int64_t fit = (int64_t)((kScratchBytes - hdr) / (one - hdr));
+        if (grid > fit) grid = (int)fit;
+    }
+    knn_status_t st = begin_stats(h, stream);
+    if (st != KNN_SUCCESS) return st;
+    int mode = opt ? opt->pivot : kPivotSample;
+    if (mode == kPivotLearned && !h->has_net) mode = kPivotSample;
+    SelectArgs a{};
+    a.dist = dist;
+    a.rows = rows;
+    a.cols = (uint32_t)cols;
+    a.ld = ld;
+    a.k = (uint32_t)k;
+    a.out_val = out_val;
+    a.out_idx = out_idx;
+    a.net = mode == kPivotLearned ? h->net_bf16 : nullptr;
+    a.mode = mode;
+    a.stats = h->stats_dev;
+    hipError_t e = launch_select(a, cap, grid, h->scratch, stream);
     if (e != hipSuccess) return hip_fail(h, e, "select kernel launch");
     return KNN_SUCCESS;
 }

@@ -15,6 +15,7 @@ struct knn_handle_s {
     int num_cu = 0;
     std::string arch;
     void *ws = nullptr;        // general workspace, grows on demand
+    void *scratch = nullptr;   // device address of this device's static scratch array
     size_t ws_bytes = 0;
     unsigned long long *stats_dev = nullptr;  // kStatCount counters
     hipStream_t last_stream = nullptr;
