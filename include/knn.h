@@ -75,12 +75,28 @@ typedef enum {
                             /* exactly in the epilogue                                */
 } knn_precision_t;
 
+/* Distance of knn_search / knn_graph / knn_batch_search (Methods, "Distance
+ * calculation": Euclidean distance, cosine similarity, and Pearson's
+ * correlation as the cosine similarity of the mean-centred vectors). */
+typedef enum {
+    KNN_METRIC_SQEUCLIDEAN = 0, /* |x - y|^2                                             */
+    KNN_METRIC_COSINE = 1,      /* 1 - x.y / (|x| |y|)                                   */
+    KNN_METRIC_PEARSON = 2      /* 1 - r(x, y): the cosine distance of x - mean(x) and   */
+                                /* y - mean(y)                                           */
+    /* Cosine and Pearson run the Euclidean path on unit vectors u = x / |x|
+     * (centred first for Pearson) and return |u - v|^2 / 2, which equals
+     * 1 - similarity and has no cancellation near 0.  A vector without a
+     * direction (zero norm after centring, a constant vector for Pearson, or a
+     * non-finite element) has NaN distances, which sort after every number. */
+} knn_metric_t;
+
 typedef struct {
     int32_t pivot;      /* knn_pivot_t; default KNN_PIVOT_SAMPLE                      */
     int32_t precision;  /* knn_precision_t; default KNN_PREC_FP32 (search / graph)    */
     int32_t oversample; /* candidates kept before the exact re-rank = oversample * k; */
                         /* default 4, at least 1                                      */
     int32_t flags;      /* KNN_FLAG_* bits                                            */
+    int32_t metric;     /* knn_metric_t; default KNN_METRIC_SQEUCLIDEAN               */
 } knn_options_t;
 
 /* Force the exact-fallback path of search / graph for every row that takes
@@ -226,10 +242,13 @@ knn_status_t knn_partition(knn_handle_t h, const float *in, int64_t rows, int64_
  *   queries   m x d FP32                                           [in, device]
  *   corpus    n x d FP32                                           [in, device]
  *   k         1 <= k <= min(n, 1024)
- *   out_dist  m x k FP32 squared distances                          [out]
+ *   out_dist  m x k FP32 squared distances (cosine / Pearson: 1 - similarity,
+ *             see knn_metric_t)                                     [out]
  *   out_idx   m x k int32 corpus indices                            [out]
  * Errors: INVALID_VALUE for null pointers, m < 0, n < 1, d < 1, k < 1, k > n,
- * a bad option; UNSUPPORTED for k > 1024 or n > INT32_MAX.
+ * a bad option; UNSUPPORTED for k > 1024 or n > INT32_MAX.  With a cosine or
+ * Pearson metric the handle keeps a second buffer of (m + n) d floats (n d for
+ * knn_graph) for the unit vectors.
  */
 knn_status_t knn_search(knn_handle_t h, const float *queries, int64_t m, const float *corpus,
                         int64_t n, int32_t d, int32_t k, float *out_dist, int32_t *out_idx,

@@ -17,6 +17,7 @@ from ._abi import (PIVOT_LEARNED, PIVOT_PLAIN, PIVOT_SAMPLE, PREC_BF16, PREC_FP3
 
 _PIVOTS = {"plain": PIVOT_PLAIN, "sample": PIVOT_SAMPLE, "learned": PIVOT_LEARNED}
 _PRECS = {"fp32": PREC_FP32, "bf16": PREC_BF16, "fp8": PREC_FP8_E4M3}
+_METRICS = {"sqeuclidean": _abi.METRIC_SQEUCLIDEAN, "cosine": _abi.METRIC_COSINE, "pearson": _abi.METRIC_PEARSON}
 
 
 class KnnError(RuntimeError):
@@ -71,8 +72,9 @@ class Handle:
         return ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
 
     @staticmethod
-    def _opts(pivot="sample", precision="fp32", oversample=4, flags=0):
+    def _opts(pivot="sample", precision="fp32", oversample=4, flags=0, metric="sqeuclidean"):
         o = Options()
+        o.metric = _METRICS[metric] if isinstance(metric, str) else int(metric)
         o.pivot = _PIVOTS[pivot] if isinstance(pivot, str) else int(pivot)
         o.precision = _PRECS[precision] if isinstance(precision, str) else int(precision)
         o.oversample = int(oversample)
@@ -119,8 +121,10 @@ class Handle:
                                            self._stream()))
         return ov, oi, L
 
-    def search(self, queries, corpus, k: int, pivot="sample", precision="fp32", oversample=4, flags=0):
-        """k nearest corpus rows per query row (squared Euclidean).
+    def search(self, queries, corpus, k: int, pivot="sample", precision="fp32", oversample=4, flags=0,
+               metric="sqeuclidean"):
+        """k nearest corpus rows per query row (squared Euclidean, or with
+        metric "cosine" / "pearson" the distance 1 - similarity).
         Returns (dist [m, k] f32, idx [m, k] i32)."""
         torch = _torch()
         for t in (queries, corpus):
@@ -132,14 +136,15 @@ class Handle:
             raise ValueError("queries and corpus differ in dimension")
         dist = torch.empty((m, k), dtype=torch.float32, device=queries.device)
         idx = torch.empty((m, k), dtype=torch.int32, device=queries.device)
-        o = self._opts(pivot, precision, oversample, flags)
+        o = self._opts(pivot, precision, oversample, flags, metric)
         self._check(self.lib.knn_search(self.h, ctypes.c_void_p(queries.data_ptr()), m,
                                         ctypes.c_void_p(corpus.data_ptr()), n, d, k,
                                         ctypes.c_void_p(dist.data_ptr()), ctypes.c_void_p(idx.data_ptr()),
                                         self._stream(), ctypes.byref(o)))
         return dist, idx
 
-    def batch_search(self, jobs, pivot="sample", precision="fp32", oversample=4, flags=0, out=None):
+    def batch_search(self, jobs, pivot="sample", precision="fp32", oversample=4, flags=0, out=None,
+                     metric="sqeuclidean"):
         """Many independent k-NN problems in one call.  `jobs` is a list of
         (queries, corpus, k) tuples of contiguous float32 device tensors, with
         queries None for the k-NN graph of the corpus.  Returns a list of
@@ -164,7 +169,7 @@ class Handle:
             arr[j] = Job(0 if q is None else q.data_ptr(), m, c.data_ptr(), n, d, kj, dist.data_ptr(),
                          idx.data_ptr())
             res.append((dist, idx))
-        o = self._opts(pivot, precision, oversample, flags)
+        o = self._opts(pivot, precision, oversample, flags, metric)
         self._check(self.lib.knn_batch_search(self.h, arr, len(jobs), self._stream(), ctypes.byref(o)))
         return res
 
@@ -291,7 +296,8 @@ class Handle:
         self._check(self.lib.knn_pivot_train(self.h, None if out_path is None else str(out_path).encode(),
                                              int(seed), int(steps)))
 
-    def graph(self, points, k: int, pivot="sample", precision="fp32", oversample=4, flags=0):
+    def graph(self, points, k: int, pivot="sample", precision="fp32", oversample=4, flags=0,
+              metric="sqeuclidean"):
         """k-NN graph of the rows of `points` (own index excluded).
         Returns (dist [n, k] f32, idx [n, k] i32)."""
         torch = _torch()
@@ -300,7 +306,7 @@ class Handle:
         n, d = points.shape
         dist = torch.empty((n, k), dtype=torch.float32, device=points.device)
         idx = torch.empty((n, k), dtype=torch.int32, device=points.device)
-        o = self._opts(pivot, precision, oversample, flags)
+        o = self._opts(pivot, precision, oversample, flags, metric)
         self._check(self.lib.knn_graph(self.h, ctypes.c_void_p(points.data_ptr()), n, d, k,
                                        ctypes.c_void_p(dist.data_ptr()), ctypes.c_void_p(idx.data_ptr()),
                                        self._stream(), ctypes.byref(o)))

@@ -15,6 +15,7 @@ KNN_ERROR_IO = 5
 
 PIVOT_PLAIN, PIVOT_SAMPLE, PIVOT_LEARNED = 0, 1, 2
 PREC_FP32, PREC_BF16, PREC_FP8_E4M3 = 0, 1, 2
+METRIC_SQEUCLIDEAN, METRIC_COSINE, METRIC_PEARSON = 0, 1, 2
 FLAG_FORCE_FALLBACK = 0x1
 FLAG_UNFUSED = 0x2
 FLAG_TIMING = 0x4
@@ -28,7 +29,8 @@ PIVOT_NPARAM = 4801
 
 class Options(ctypes.Structure):
     _fields_ = [("pivot", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("oversample", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("oversample", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("metric", ctypes.c_int32)]
 
 
 class Job(ctypes.Structure):

@@ -78,31 +78,42 @@ void add_product_time(knn_handle_t h, double ms, double flops) {
     h->host_product_launches += 1;
 }
 
-// Ensures the handle's workspace holds at least `bytes`; returns its pointer.
-knn_status_t ensure_ws(knn_handle_t h, size_t bytes, hipStream_t stream, void **out) {
-    if (bytes <= h->ws_bytes) {
-        *out = h->ws;
+// Ensures the handle buffer (*buf, *cap bytes) holds at least `bytes`; returns its pointer.
+static knn_status_t ensure_buf(knn_handle_t h, void **buf, size_t *cap, size_t bytes, hipStream_t stream, void **out) {
+    if (bytes <= *cap) {
+        *out = *buf;
         return KNN_SUCCESS;
     }
     // earlier work on the previous stream may still use the old buffer
-    if (h->ws) {
+    if (*buf) {
         hipError_t e = hipStreamSynchronize(h->last_stream);
         if (e == hipSuccess && stream != h->last_stream) e = hipStreamSynchronize(stream);
         if (e != hipSuccess) return hip_fail(h, e, "hipStreamSynchronize");
-        hipFree(h->ws);
-        h->ws = nullptr;
-        h->ws_bytes = 0;
+        hipFree(*buf);
+        *buf = nullptr;
+        *cap = 0;
     }
     size_t want = bytes + bytes / 4;  // headroom to avoid regrowing
-    hipError_t e = hipMalloc(&h->ws, want);
+    hipError_t e = hipMalloc(buf, want);
     if (e != hipSuccess) {
-        h->ws = nullptr;
+        *buf = nullptr;
         (void)hipGetLastError();
         return fail(h, KNN_ERROR_OUT_OF_MEMORY, "workspace allocation of " + std::to_string(want) + " bytes failed");
     }
-    h->ws_bytes = want;
-    *out = h->ws;
+    *cap = want;
+    *out = *buf;
     return KNN_SUCCESS;
+}
+
+// The handle's general workspace.
+knn_status_t ensure_ws(knn_handle_t h, size_t bytes, hipStream_t stream, void **out) {
+    return ensure_buf(h, &h->ws, &h->ws_bytes, bytes, stream, out);
+}
+
+// The unit-vector copies of the cosine and Pearson distances (kept apart from
+// the general workspace, which the Euclidean path on them may regrow).
+knn_status_t ensure_unit_ws(knn_handle_t h, size_t bytes, hipStream_t stream, void **out) {
+    return ensure_buf(h, &h->uws, &h->uws_bytes, bytes, stream, out);
 }
 }  // namespace knn
 
@@ -164,6 +175,7 @@ knn_status_t knn_destroy(knn_handle_t h) {
     hipDeviceSynchronize();
     batch_release(h);
     if (h->ws) hipFree(h->ws);
+    if (h->uws) hipFree(h->uws);
     if (h->stats_dev) hipFree(h->stats_dev);
     if (h->pinned) hipHostFree(h->pinned);
     for (void *p : {(void *)h->net_theta, (void *)h->net_theta_r, (void *)h->net_m, (void *)h->net_v,
@@ -321,6 +333,8 @@ static knn_status_t check_options(knn_handle_t h, const char *fn, const knn_opti
     if (opt->oversample < 0) return fail(h, KNN_ERROR_INVALID_VALUE, std::string(fn) + ": oversample < 0");
     if (opt->precision < KNN_PREC_FP32 || opt->precision > KNN_PREC_FP8_E4M3)
         return fail(h, KNN_ERROR_INVALID_VALUE, std::string(fn) + ": bad precision");
+    if (opt->metric < KNN_METRIC_SQEUCLIDEAN || opt->metric > KNN_METRIC_PEARSON)
+        return fail(h, KNN_ERROR_INVALID_VALUE, std::string(fn) + ": bad metric");
     return KNN_SUCCESS;
 }
 

@@ -45,6 +45,7 @@ int handle_num_cu(knn_handle_t h);
 const uint16_t *handle_net(knn_handle_t h);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t stream);
 hipError_t launch_sum_u32(const uint32_t *p, int64_t n, unsigned long long *out, hipStream_t stream);
+knn_status_t ensure_unit_ws(knn_handle_t h, size_t bytes, hipStream_t stream, void **out);
 knn_status_t run_search(knn_handle_t h, const float *Q, int64_t m, const float *C, int64_t n, int d, int k, bool graph,
                         float *out_dist, int32_t *out_idx, hipStream_t stream, const knn_options_t *opt);
 
@@ -57,6 +58,7 @@ struct BatchJob {
     int32_t *out_idx;
     Plan p;
     double cost;  // 2 m n d
+    float oscale = 1.0f;  // returned distance = oscale * squared distance (cosine / Pearson: 1/2)
     // per-job buffers
     float *cnorm = nullptr, *qn2 = nullptr;
     unsigned int *cmax2 = nullptr;
@@ -443,7 +445,7 @@ hipError_t certify_rerank(const BatchState &b, knn_handle_t h, size_t pi, const 
         if ((e = launch_certify(ca, s)) != hipSuccess) return e;
     }
     RerankArgs rr{js.Q + pt.i0 * js.d, pt.mb, js.C, js.n, js.d, cidx, (uint32_t)p.kk, js.k,
-                  js.out_dist + pt.i0 * js.k, js.out_idx + pt.i0 * js.k, js.graph ? pt.i0 : -1};
+                  js.out_dist + pt.i0 * js.k, js.out_idx + pt.i0 * js.k, js.graph ? pt.i0 : -1, js.oscale};
     return launch_rerank(rr, s);
 }
 
@@ -592,6 +594,7 @@ hipError_t run_rerun(const BatchState &b, hipStream_t s, int64_t *total) {
         const Plan &p = js.p;
         const float *Qb = js.Q + pt.i0 * js.d;
         FixupArgs fx{};
+        fx.out_scale = js.oscale;
         fx.tfix = pt.tfix;
         fx.Q = Qb;
         fx.C = js.C;
@@ -702,6 +705,35 @@ knn_status_t run_batch(knn_handle_t h, const knn_job_t *jobs, int32_t njobs, hip
         return KNN_SUCCESS;
     }
 
+    // cosine / Pearson: every job on unit vectors (centred for Pearson), made
+    // on each call before the captured steps run
+    std::vector<knn_job_t> unit_jobs;
+    if (o.metric != KNN_METRIC_SQEUCLIDEAN) {
+        size_t total = 0;
+        for (int32_t j = 0; j < njobs; ++j)
+            if (jobs[j].m > 0) total += (size_t)(jobs[j].n + (jobs[j].queries ? jobs[j].m : 0)) * (size_t)jobs[j].d;
+        void *u = nullptr;
+        knn_status_t us = ensure_unit_ws(h, total * sizeof(float) + 256, stream, &u);
+        if (us != KNN_SUCCESS) return us;
+        float *U = static_cast<float *>(u);
+        const bool centre = o.metric == KNN_METRIC_PEARSON;
+        unit_jobs.assign(jobs, jobs + njobs);
+        size_t off = 0;
+        for (int32_t j = 0; j < njobs; ++j) {
+            knn_job_t &jb = unit_jobs[(size_t)j];
+            if (jb.m == 0) continue;
+            KTRY(launch_unit_rows(jb.corpus, jb.n, jb.d, centre, U + off, stream));
+            jb.corpus = U + off;
+            off += (size_t)jb.n * jb.d;
+            if (jb.queries) {
+                KTRY(launch_unit_rows(jb.queries, jb.m, jb.d, centre, U + off, stream));
+                jb.queries = U + off;
+                off += (size_t)jb.m * jb.d;
+            }
+        }
+        jobs = unit_jobs.data();
+    }
+
     if (!h->batch) h->batch = new BatchState();
     BatchState &b = *h->batch;
     std::vector<uint8_t> key = make_key(jobs, njobs, o, smode, net, b.ws);
@@ -733,6 +765,7 @@ knn_status_t run_batch(knn_handle_t h, const knn_job_t *jobs, int32_t njobs, hip
             js.out_idx = jb.out_idx;
             js.p = make_plan(jb.m > 0 ? jb.m : 1, jb.n, jb.d, jb.k, js.graph, &o, kRowBlock);
             js.cost = 2.0 * (double)jb.m * (double)jb.n * jb.d;
+            js.oscale = o.metric != KNN_METRIC_SQEUCLIDEAN ? 0.5f : 1.0f;
             js.first_part = (int)b.parts.size();
             for (int64_t i0 = 0; i0 < jb.m; i0 += js.p.Mb) {
                 BatchPart pt{};

@@ -343,6 +343,81 @@ __global__ __launch_bounds__(64 * WM * WN) void dist_gemm_grouped_kernel(const D
     gemm_tile<WM, WN, BI, BJ, EPI, PREC, VEC, 2>(a, w.tm, w.tn, sm);
 }
 
+// ---- unit vectors (cosine and Pearson distances) ------------------------------
+// Methods, "Distance calculation": the cosine similarity of x and y is
+// x.y / (|x| |y|), and Pearson's correlation is the cosine similarity of the
+// vectors minus their means.  With u = x / |x| and v = y / |y|,
+// 1 - cos = |u - v|^2 / 2, so both distances are half the squared Euclidean
+// distance of unit vectors, and the Euclidean path ranks them unchanged.  One
+// wave per row: lane-strided sums in a fixed order reduced by a lane tree; the
+// norm is taken of the row scaled by its largest magnitude (no overflow or
+// underflow in the squares), and every element is divided once.
+__device__ __forceinline__ float wave_sum(float s) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    return s;
+}
+__device__ __forceinline__ float wave_max(float s) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s = fmaxf(s, __shfl_xor(s, off));
+    return s;
+}
+__device__ __forceinline__ float wave_min(float s) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s = fminf(s, __shfl_xor(s, off));
+    return s;
+}
+
+__global__ __launch_bounds__(256) void unit_rows_kernel(const float *__restrict__ X, int64_t n, int d, int centre,
+                                                        float *__restrict__ out) {
+    const uint32_t lane = lane_id();
+    const int64_t i = (int64_t)blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
+    if (i >= n) return;
+    const float *x = X + i * d;
+    float *o = out + i * d;
+    float mu = 0.f;
+    bool flat = false;
+    if (centre) {
+        float s = 0.f, lo = __uint_as_float(0x7f800000u), hi = -lo;
+        for (int t = (int)lane; t < d; t += kWave) {
+            const float v = x[t];
+            s += v;
+            lo = fminf(lo, v);
+            hi = fmaxf(hi, v);
+        }
+        mu = wave_sum(s) / (float)d;
+        // a constant row is exactly zero once centred, whatever the rounding of its mean
+        flat = wave_min(lo) == wave_max(hi);
+    }
+    float amax = 0.f;
+    bool nan = false;
+    for (int t = (int)lane; t < d; t += kWave) {
+        const float v = x[t] - mu;
+        nan |= v != v;
+        amax = fmaxf(amax, fabsf(v));
+    }
+    amax = wave_max(amax);
+    nan = __ballot(nan) != 0;
+    const bool ok = !flat && !nan && amax > 0.f && amax <= 3.4028235e38f;
+    float ss = 0.f;
+    if (ok)
+        for (int t = (int)lane; t < d; t += kWave) {
+            const float v = (x[t] - mu) / amax;
+            ss = fmaf(v, v, ss);
+        }
+    const float nrm = sqrtf(wave_sum(ss));
+    const float qnan = __uint_as_float(0x7fc00000u);
+    for (int t = (int)lane; t < d; t += kWave) o[t] = ok ? ((x[t] - mu) / amax) / nrm : qnan;
+}
+
+hipError_t launch_unit_rows(const float *X, int64_t n, int d, bool centre, float *out, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    const int64_t blocks = (n + 3) / 4;
+    if (blocks > 0x7fffffffll) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(unit_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, X, n, d, centre ? 1 : 0, out);
+    return hipGetLastError();
+}
+
 // ---- squared norms ----------------------------------------------------------
 // G lanes per point (the power of two covering the point's 16-byte chunks, or
 // its elements without 16-byte loads; at most 64), 64 / G points per wave,
@@ -529,7 +604,7 @@ __global__ __launch_bounds__(kRerankThreads) void rerank_kernel(RerankArgs a) {
             a.out_dist[i * a.k + t] = __uint_as_float(0x7f800000u);
             a.out_idx[i * a.k + t] = -1;
         } else {
-            a.out_dist[i * a.k + t] = ord_to_float(key_ord(key));
+            a.out_dist[i * a.k + t] = a.out_scale * ord_to_float(key_ord(key));
             a.out_idx[i * a.k + t] = (int32_t)key_idx(key);
         }
     }
@@ -720,7 +795,7 @@ __global__ __launch_bounds__(kFixThreads) void exact_rows_kernel(FixupArgs a) {
             a.out_dist[o] = __uint_as_float(0x7f800000u);
             a.out_idx[o] = -1;
         } else {
-            a.out_dist[o] = ord_to_float(key_ord(key));
+            a.out_dist[o] = a.out_scale * ord_to_float(key_ord(key));
             a.out_idx[o] = (int32_t)key_idx(key);
         }
     }

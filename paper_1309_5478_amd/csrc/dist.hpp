@@ -61,6 +61,7 @@ struct RerankArgs {
     float *out_dist;        // m x k
     int32_t *out_idx;       // m x k
     int64_t self_offset = -1;  // >= 0: row i's own corpus index self_offset + i is never returned
+    float out_scale = 1.0f;    // returned distance = out_scale * the direct-form sum (a power of two)
 };
 
 hipError_t launch_dist_gemm(const DistArgs &a, int epi, hipStream_t stream);
@@ -140,7 +141,14 @@ struct FixupArgs {
     int64_t self_offset;     // >= 0: row i's own corpus index self_offset + i is excluded
     float *out_dist;         // block outputs, row id i at out + i k
     int32_t *out_idx;
+    float out_scale = 1.0f;  // as RerankArgs::out_scale
 };
 hipError_t launch_fixup(const FixupArgs &a, hipStream_t stream);
+
+// Unit vectors for the cosine (centre = false) and Pearson (centre = true)
+// distances: each row of X minus its mean (Pearson), divided by its Euclidean
+// norm, into out (n x d FP32).  A row without a direction (zero or non-finite
+// norm after centring; a constant row for Pearson) becomes all NaN.
+hipError_t launch_unit_rows(const float *X, int64_t n, int d, bool centre, float *out, hipStream_t stream);
 
 }  // namespace knn

@@ -15,6 +15,8 @@ struct knn_handle_s {
     int num_cu = 0;
     std::string arch;
     void *ws = nullptr;        // general workspace, grows on demand
+    void *uws = nullptr;       // unit-vector copies (cosine / Pearson), grows on demand
+    size_t uws_bytes = 0;
     void *scratch = nullptr;   // device address of this device's static scratch array
     size_t ws_bytes = 0;
     unsigned long long *stats_dev = nullptr;  // kStatCount counters

@@ -34,6 +34,7 @@
 namespace knn {
 
 knn_status_t ensure_ws(knn_handle_t h, size_t bytes, hipStream_t stream, void **out);
+knn_status_t ensure_unit_ws(knn_handle_t h, size_t bytes, hipStream_t stream, void **out);
 knn_status_t fail_msg(knn_handle_t h, knn_status_t s, const std::string &msg);
 uint32_t *host_counter(knn_handle_t h);
 unsigned long long *stats_ptr(knn_handle_t h);
@@ -49,6 +50,24 @@ hipError_t launch_sum_u32(const uint32_t *p, int64_t n, unsigned long long *out,
 knn_status_t run_search(knn_handle_t h, const float *Q, int64_t m, const float *C, int64_t n, int d, int k, bool graph,
                         float *out_dist, int32_t *out_idx, hipStream_t stream, const knn_options_t *opt) {
     const int num_cu = handle_num_cu(h);
+    // cosine / Pearson: the same path on unit vectors (centred for Pearson),
+    // returning half their squared distance, 1 - similarity
+    float oscale = 1.0f;
+    const int metric = opt ? opt->metric : KNN_METRIC_SQEUCLIDEAN;
+    if (metric != KNN_METRIC_SQEUCLIDEAN) {
+        void *u = nullptr;
+        const size_t need = (size_t)(graph ? n : n + m) * (size_t)d * sizeof(float);
+        knn_status_t us = ensure_unit_ws(h, need, stream, &u);
+        if (us != KNN_SUCCESS) return us;
+        float *U = static_cast<float *>(u);
+        const bool centre = metric == KNN_METRIC_PEARSON;
+        hipError_t ue = launch_unit_rows(C, n, d, centre, U, stream);
+        if (ue == hipSuccess && !graph) ue = launch_unit_rows(Q, m, d, centre, U + (size_t)n * d, stream);
+        if (ue != hipSuccess) return fail_msg(h, KNN_ERROR_DEVICE, std::string("unit rows: ") + hipGetErrorString(ue));
+        C = U;
+        Q = graph ? U : U + (size_t)n * d;
+        oscale = 0.5f;
+    }
     // pivot rule of every quick multi-select in the path (the learned rule needs
     // a loaded pivot network; without one it is the sample rule)
     const uint16_t *net = handle_net(h);
@@ -123,7 +142,7 @@ knn_status_t run_search(knn_handle_t h, const float *Q, int64_t m, const float *
             KNN_TRY(launch_certify(ca, stream));
         }
         RerankArgs rr{Qb, mb, C, n, d, cidx, (uint32_t)p.kk, k, out_dist + i0 * k, out_idx + i0 * k,
-                      graph ? i0 : -1};
+                      graph ? i0 : -1, oscale};
         KNN_TRY(launch_rerank(rr, stream));
         if (!refix) return KNN_SUCCESS;
         KNN_TRY(hipMemcpyAsync(hcount, b.nu, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
@@ -131,6 +150,7 @@ knn_status_t run_search(knn_handle_t h, const float *Q, int64_t m, const float *
         const int64_t nu = *hcount;
         rerun_total += nu;
         FixupArgs fx{};
+        fx.out_scale = oscale;
         fx.tfix = b.tfix;
         fx.Q = Qb;
         fx.C = C;

@@ -59,3 +59,53 @@ def compare(Q, C, k, gd, gi, rows, self_ids=None):
                 if g_idx[a] != want[a]:
                     assert abs(d64(Q[r], C[g_idx[a]]) - d64(Q[r], C[want[a]])) <= REL * max(od[t, a], 1e-30)
     return near
+
+
+def metric_tol(ref, d):
+    """Cosine / Pearson distance bar: 1e-5 relative, plus the FP32 error of the
+    unit vectors the GPU ranks (per element at most eps_d relative, eps_d =
+    (ceil(d / 64) + 16) 2^-24 for the norm's lane sums, the two divisions and
+    the centring), which moves |u - v|^2 / 2 by at most 2 eps_d |u - v|."""
+    eps = (np.ceil(d / 64.0) + 16.0) * 2.0 ** -24
+    return REL * np.abs(ref) + 2.0 * eps * np.sqrt(2.0 * np.maximum(ref, 0.0)) + 4.0 * eps * np.abs(ref)
+
+
+def compare_metric(Q, C, k, gd, gi, rows, metric, self_ids=None):
+    """compare() for the cosine / Pearson distances (1 - similarity): sets equal
+    outside the near-tie band of metric_tol at the k-th distance, distances of
+    the returned points within metric_tol of the oracle's, NaN exactly where the
+    oracle's is NaN, rows ascending.  Returns the near-tie row count."""
+    qs = Q[rows]
+    d = Q.shape[1]
+    sid = None if self_ids is None else np.asarray(self_ids)[rows]
+    n_elig = C.shape[0] - (0 if sid is None else 1)
+    kk = min(k + 1, n_elig)
+    od, oi = oracle.knn(qs, C, kk, self_ids=sid, metric=metric)
+    near = 0
+    for t, r in enumerate(rows):
+        g_idx = [int(x) for x in gi[t]]
+        assert len(set(g_idx)) == k, f"row {r}: duplicate indices"
+        if sid is not None:
+            assert int(sid[t]) not in g_idx, f"row {r}: own index returned"
+        # the oracle's distances of exactly the returned points
+        sub_d, sub_i = oracle.knn(Q[r:r + 1], C[g_idx], k, metric=metric)
+        ref = np.empty(k)
+        ref[sub_i[0]] = sub_d[0]
+        g = gd[t].astype(np.float64)
+        assert np.array_equal(np.isnan(g), np.isnan(ref)), f"row {r}: NaN pattern"
+        fin = ~np.isnan(ref)
+        assert np.all(np.abs(g[fin] - ref[fin]) <= metric_tol(ref[fin], d)), \
+            (r, float(np.max(np.abs(g[fin] - ref[fin]))))
+        for a in range(k - 1):   # ascending, NaN last, ties by index
+            x, y = g[a], g[a + 1]
+            assert np.isnan(y) or (not np.isnan(x) and (x < y or (x == y and g_idx[a] < g_idx[a + 1]))), (r, a)
+        want = [int(x) for x in oi[t, :k]]
+        if set(g_idx) != set(want):
+            kth = od[t, k - 1]
+            assert not np.isnan(kth), f"row {r}: set differs in the NaN class"
+            band = metric_tol(np.array([kth]), d)[0]
+            for j in set(g_idx) ^ set(want):
+                dj = oracle.knn(Q[r:r + 1], C[j:j + 1], 1, metric=metric)[0][0, 0]
+                assert abs(dj - kth) <= band, f"row {r}: set differs beyond the near-tie band ({j}: {dj} vs {kth})"
+            near += 1
+    return near
