@@ -5,24 +5,26 @@
 // candidate selection, exact re-rank), so its output is the same.  What changes
 // is how the work reaches the device:
 //  * the fused products of all jobs run as ONE launch of (job part, row tile,
-//    column tile) items, one per workgroup, that the host orders for the
-//    hardware's round-robin dispatch over the eight XCDs: per XCD a queue of
-//    parts, longest first, a part's column range split into eight contiguous
-//    chunks, one per XCD, so each corpus tile is read by one XCD, where the
-//    part's row tiles reuse it from L2;
-//  * the per-job steps before and after it (norms, sample product, threshold
-//    selection, list flagging; candidate selection, certificate, re-rank) are
-//    captured into HIP graphs on the first call and replayed by later calls
-//    with the same job table (one graph launch per phase instead of thousands
-//    of kernel launches);
-//  * with autotuning on, the tile shape of the grouped launch is the fastest
-//    of the candidate shapes, timed on the batch itself with a threshold of
-//    -inf (nothing is kept, so the timing run has no effect on the results).
+//    column tile) items that the host orders for the hardware's round-robin
+//    dispatch over the eight XCDs: per XCD a queue of parts, longest first, a
+//    part's column range split into eight contiguous chunks, one per XCD, so
+//    each corpus tile is read by one XCD, where the part's row tiles reuse it
+//    from L2.  The items run one per workgroup, or (queue form) a resident
+//    grid takes them from eight per-XCD atomic queues in the same order;
+//  * every step of a call (norms, sample product, threshold selection, the
+//    product, list flagging, candidate selection, certificate, re-rank) is
+//    captured into one HIP graph on the first call and replayed by later calls
+//    with the same job table; one synchronisation then brings the counts of
+//    rows needing the exact fallback or re-run (rare) to the host;
+//  * with autotuning on, the tile shape and form of the grouped launch are
+//    the fastest of the candidates, timed on the batch itself with a threshold
+//    of -inf (nothing is kept, so the timing run has no effect on the results).
 // Jobs with more than kRowBlock queries are split into parts of at most that
 // many rows; each part has its own candidate lists.  Jobs whose threshold
 // sample is their whole corpus are finished in the first phase, as in
 // knn_search.
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <string>
@@ -112,6 +114,7 @@ struct BatchShared {
     GemmItem *items = nullptr, *sitems = nullptr;
     uint32_t *nflag = nullptr;
     uint32_t *nu = nullptr;  // uncertified-row counts, one per part
+    uint32_t *queues = nullptr;  // the eight per-XCD item queues of the persistent product
 };
 
 // State of the last batch of a handle: its workspace, plan and graphs.
@@ -130,6 +133,7 @@ struct BatchState {
     std::vector<int> order;  // jobs, longest first
     BatchShared sh;
     int tile = kTileWide;
+    bool queue = false;  // the product as a resident grid over per-XCD item queues
     size_t nitems = 0, nsitems = 0;
     std::vector<SegLaunch> sample_sel;  // threshold selections, one launch per capacity class
     SegLaunch keys_sel;                 // candidate selections
@@ -163,6 +167,9 @@ namespace {
 // their XCD's L2).  Workgroup b runs on XCD b % 8 and takes the next item of
 // that queue; once a queue is empty its XCD takes items from the back of the
 // fullest remaining queue (the shortest work there).
+// Autotune candidates: a tile shape, plus this for the queue form.
+constexpr int kQueueChoice = 16;
+
 void build_items(const BatchState &b, int tile, std::vector<GemmItem> &items) {
     constexpr int kQueues = 8;
     int bm, bn;
@@ -371,6 +378,7 @@ size_t carve_batch(Carve &c, BatchState &b, int num_cu, bool probe) {
     b.nsitems = si.size();
     s.nflag = c.take<uint32_t>(b.parts.size());
     s.nu = c.take<uint32_t>(b.parts.size());
+    s.queues = c.take<uint32_t>(8);
     return c.off;
 }
 
@@ -495,9 +503,14 @@ hipError_t enqueue_prep(const BatchState &b, knn_handle_t h, int num_cu, hipStre
     return e;
 }
 
-hipError_t enqueue_product(const BatchState &b, const DistArgs *table, int tile, hipStream_t s) {
+hipError_t enqueue_product(const BatchState &b, const DistArgs *table, int tile, bool queue, int num_cu,
+                           hipStream_t s) {
     hipError_t e = hipSuccess;
-    BTRY(launch_dist_gemm_grouped(table, b.sh.items, (int64_t)b.nitems, b.jobs[0].p.prec, tile, s));
+    if (queue)
+        BTRY(launch_dist_gemm_queue(table, b.sh.items, (int64_t)b.nitems, b.jobs[0].p.prec, tile, b.sh.queues, num_cu,
+                                    s));
+    else
+        BTRY(launch_dist_gemm_grouped(table, b.sh.items, (int64_t)b.nitems, b.jobs[0].p.prec, tile, s));
     for (const BatchPart &pt : b.parts) {
         if (pt.grouped || pt.direct) continue;
         DistArgs fa = part_args(b, pt);
@@ -846,6 +859,15 @@ knn_status_t run_batch(knn_handle_t h, const knn_job_t *jobs, int32_t njobs, hip
         KTRY(launch_fill_u32(reinterpret_cast<uint32_t *>(b.sh.ninf), 1, 0xFF800000u, stream));
         const int prec = b.jobs[0].p.prec;
         b.tile = prec == kPrecFP8 ? kTileWide : kTileBig;
+        b.queue = false;
+        // overrides of the default form (tests, measurements): KNN_GEMM_TILE
+        // small / wide / big, KNN_BATCH_QUEUE 1 / 0
+        if (const char *te = std::getenv("KNN_GEMM_TILE")) {
+            if (!std::strcmp(te, "small")) b.tile = kTileSmall;
+            else if (!std::strcmp(te, "wide")) b.tile = kTileWide;
+            else if (!std::strcmp(te, "big") && prec != kPrecFP8) b.tile = kTileBig;
+        }
+        if (const char *qe = std::getenv("KNN_BATCH_QUEUE")) b.queue = qe[0] == '1';
         std::vector<GemmItem> items;
         int uploaded = -1;
         auto upload = [&](int tile) -> hipError_t {
@@ -883,16 +905,22 @@ knn_status_t run_batch(knn_handle_t h, const knn_job_t *jobs, int32_t njobs, hip
                 KTRY(hipMemcpyAsync(b.sh.probe, probe.data(), probe.size() * sizeof(DistArgs), hipMemcpyHostToDevice,
                                     stream));
                 KTRY(hipStreamSynchronize(stream));
+                // every tile shape, as one workgroup per item (c) and as a
+                // resident grid over the per-XCD queues (c + kQueueChoice)
                 std::vector<int> cands = {kTileSmall, kTileWide};
                 if (prec != kPrecFP8) cands.push_back(kTileBig);
-                auto run = [&](int tile) -> hipError_t {
+                const size_t nshape = cands.size();
+                for (size_t i = 0; i < nshape; ++i) cands.push_back(cands[i] + kQueueChoice);
+                auto run = [&](int c) -> hipError_t {
+                    const int tile = c % kQueueChoice;
                     hipError_t re = upload(tile);
-                    if (re == hipSuccess) re = enqueue_product(b, b.sh.probe, tile, stream);
+                    if (re == hipSuccess) re = enqueue_product(b, b.sh.probe, tile, c >= kQueueChoice, num_cu, stream);
                     return re;
                 };
                 KTRY(autotune_pick(tkey, cands, run, stream, 2, &choice));
             }
-            b.tile = choice;
+            b.tile = choice % kQueueChoice;
+            b.queue = choice >= kQueueChoice;
         }
         KTRY(upload(b.tile));
 
@@ -902,22 +930,28 @@ knn_status_t run_batch(knn_handle_t h, const knn_job_t *jobs, int32_t njobs, hip
             std::vector<hipGraphExec_t> gs;
             hipGraphExec_t g = nullptr;
             bool ok = true;
+            // one graph for the whole call (two around the timed product); rows
+            // flagged for the exact fallback come out of it with provisional
+            // results, re-done eagerly afterwards
             if (timed) {
                 ok = capture(b, [&](hipStream_t s) { return enqueue_prep(b, h, num_cu, s); }, &g) == hipSuccess;
                 if (ok) gs.push_back(g);
-                ok = ok && capture(b, [&](hipStream_t s) { return enqueue_flags(b, h, s); }, &g) == hipSuccess;
+                ok = ok && capture(b, [&](hipStream_t s) {
+                               hipError_t ce = enqueue_flags(b, h, s);
+                               if (ce == hipSuccess) ce = enqueue_final(b, h, num_cu, s);
+                               return ce;
+                           }, &g) == hipSuccess;
                 if (ok) gs.push_back(g);
             } else {
                 ok = capture(b, [&](hipStream_t s) {
                          hipError_t ce = enqueue_prep(b, h, num_cu, s);
-                         if (ce == hipSuccess) ce = enqueue_product(b, b.sh.table, b.tile, s);
+                         if (ce == hipSuccess) ce = enqueue_product(b, b.sh.table, b.tile, b.queue, num_cu, s);
                          if (ce == hipSuccess) ce = enqueue_flags(b, h, s);
+                         if (ce == hipSuccess) ce = enqueue_final(b, h, num_cu, s);
                          return ce;
                      }, &g) == hipSuccess;
                 if (ok) gs.push_back(g);
             }
-            ok = ok && capture(b, [&](hipStream_t s) { return enqueue_final(b, h, num_cu, s); }, &g) == hipSuccess;
-            if (ok) gs.push_back(g);
             if (ok) {
                 b.graphs = gs;
                 b.eager = false;
@@ -938,31 +972,37 @@ knn_status_t run_batch(knn_handle_t h, const knn_job_t *jobs, int32_t njobs, hip
     if (b.eager) {
         KTRY(enqueue_prep(b, h, num_cu, stream));
         KTRY(timer.begin(stream, flops));
-        KTRY(enqueue_product(b, b.sh.table, b.tile, stream));
+        KTRY(enqueue_product(b, b.sh.table, b.tile, b.queue, num_cu, stream));
         KTRY(timer.end(stream));
         KTRY(enqueue_flags(b, h, stream));
+        KTRY(enqueue_final(b, h, num_cu, stream));
     } else if (timed) {
         KTRY(hipGraphLaunch(b.graphs[0], stream));
         KTRY(timer.begin(stream, flops));
-        KTRY(enqueue_product(b, b.sh.table, b.tile, stream));
+        KTRY(enqueue_product(b, b.sh.table, b.tile, b.queue, num_cu, stream));
         KTRY(timer.end(stream));
         KTRY(hipGraphLaunch(b.graphs[1], stream));
     } else {
         KTRY(hipGraphLaunch(b.graphs[0], stream));
     }
+    // the flag and uncertified-row counts reach the host here (one
+    // synchronisation per call)
     KTRY(hipStreamSynchronize(stream));
     KTRY(timer.collect(h));
     int64_t fallback = 0;
-    KTRY(run_fallback(b, num_cu, stream, &fallback));
-    if (b.eager)
+    for (size_t pi = 0; pi < b.parts.size(); ++pi) fallback += b.nflag_host[pi];
+    if (fallback > 0) {
+        // rare: the flagged rows' candidate lists are re-done exactly, then the
+        // selection, certificate and re-rank of the filtered parts run again
+        int64_t done = 0;
+        KTRY(run_fallback(b, num_cu, stream, &done));
+        for (size_t pi = 0; pi < b.parts.size(); ++pi)
+            if (!b.parts[pi].direct) KTRY(launch_fill_u32(b.sh.nu + pi, 1, 0u, stream));
         KTRY(enqueue_final(b, h, num_cu, stream));
-    else
-        KTRY(hipGraphLaunch(b.graphs.back(), stream));
-    int64_t rerun = 0;
-    if (b.jobs[0].p.prec == kPrecF32) {
         KTRY(hipStreamSynchronize(stream));
-        KTRY(run_rerun(b, stream, &rerun));
     }
+    int64_t rerun = 0;
+    if (b.jobs[0].p.prec == kPrecF32) KTRY(run_rerun(b, stream, &rerun));
 #undef KTRY
     add_host_stats(h, rows, fallback);
     add_host_rerun(h, rerun);

@@ -78,6 +78,11 @@ void gemm_tile_dims(int tile, int *bm, int *bn);
 // d % 4 == 0.  The DENSE epilogue only with the small tile.
 hipError_t launch_dist_gemm_grouped(const DistArgs *jobs, const GemmItem *items, int64_t nitems, int prec, int tile,
                                     hipStream_t stream, int epi = kEpiFilter);
+// The same items (FILTER epilogue) taken by a resident grid from eight per-XCD
+// atomic queues instead of one workgroup per item; `queues` is 8 uint32 of
+// device memory (cleared by the launch).
+hipError_t launch_dist_gemm_queue(const DistArgs *jobs, const GemmItem *items, int64_t nitems, int prec, int tile,
+                                  uint32_t *queues, int num_cu, hipStream_t stream);
 // Tile shape launch_dist_gemm uses for `a` (kTile*).
 int gemm_tile_choice(const DistArgs &a);
 // Squared norms of n rows of d floats into out; with max_bits (non-null, zero or

@@ -475,13 +475,16 @@ __global__ __launch_bounds__(kSelThreads, KEYS ? 1 : (CAP == kSelectCap ? 5 : (C
         uint32_t sb, ss, se, Kp;  // active segment (buffer, start, end) and keys still needed
 
         if (KEYS) {
-            // key-list row (at most CAP keys, at least k of them)
+            // key-list row (at most CAP keys); a list shorter than k (a row
+            // whose candidates are re-done later) is padded with the largest
+            // key up to k, so that it is exactly the answer
             const uint32_t c = key_cnt ? key_cnt[lr] : N;
             const uint32_t n = c < N ? c : N;
+            const uint32_t len = n < k ? k : n;
             const uint64_t *src = keys + lr * ld;
-            for (uint32_t p = tid; p < n; p += kSelThreads) sm.buf[0][p] = src[p];
+            for (uint32_t p = tid; p < len; p += kSelThreads) sm.buf[0][p] = p < n ? src[p] : kKeyMax;
             __syncthreads();
-            sb = 0; ss = 0; se = n; Kp = k;
+            sb = 0; ss = 0; se = len; Kp = k;
         } else if (N <= (uint32_t)CAP) {
             for (uint32_t p = tid; p < N; p += kSelThreads) sm.buf[0][p] = make_key(row[p], p);
             __syncthreads();

@@ -200,6 +200,29 @@ def test_batch_timing_and_autotune(h, knn, torch, data):
             del os.environ["KNN_AUTOTUNE_CACHE"]
 
 
+def test_batch_queue_form_same_bits(knn, torch, data):
+    """The product as a resident grid over per-XCD item queues gives the same
+    bits as one workgroup per item, for every tile shape."""
+    jobs = job_list(data)
+    want = None
+    for tile in ("small", "wide", "big"):
+        for queue in ("0", "1"):
+            os.environ["KNN_GEMM_TILE"] = tile
+            os.environ["KNN_BATCH_QUEUE"] = queue
+            try:
+                hq = knn.Handle(0)   # a fresh plan reads the settings
+                got = hq.batch_search(jobs)
+                torch.cuda.synchronize()
+            finally:
+                del os.environ["KNN_BATCH_QUEUE"]
+                del os.environ["KNN_GEMM_TILE"]
+            if want is None:
+                want = got
+            else:
+                assert_same(got, want, f"tile {tile}, queue {queue}")
+            del hq
+
+
 def test_batch_learned_pivot(knn, torch, data):
     hl = knn.Handle(0)   # packaged pivot network
     jobs = job_list(data)
