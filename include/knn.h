@@ -255,6 +255,30 @@ knn_status_t knn_search(knn_handle_t h, const float *queries, int64_t m, const f
                         void *stream, const knn_options_t *opt);
 
 /*
+ * knn_search_host_corpus -- knn_search with the corpus in host memory, for
+ * corpora beyond (or not resident in) device memory.  The paper names the
+ * device memory as the limit of its method and partitioning of the data as the
+ * way past it (Discussion).  The corpus is copied to the device in partitions
+ * of part_rows points, two partition buffers deep: the copy of partition p + 1
+ * runs on a copy stream of the handle while partition p is searched on
+ * `stream`, and each partition's k nearest per query are merged into the
+ * running k nearest by (distance, global index).  The result is knn_search's on
+ * the whole corpus, bit for bit, whenever knn_search's rows are exact (FP32
+ * products: always); options as knn_search.
+ *   queries      m x d FP32                                        [in, device]
+ *   corpus_host  n x d FP32 in host memory; copies overlap the search only
+ *                when it is pinned (hipHostMalloc); it must stay valid until
+ *                the work enqueued on `stream` has completed           [in, host]
+ *   part_rows    points per partition (0: about 1 GiB of points, at least k)
+ *   out_dist, out_idx  m x k, as knn_search                        [out, device]
+ * The handle keeps two partition buffers and three m x k result buffers.
+ * Errors: as knn_search, plus INVALID_VALUE for part_rows < 0.
+ */
+knn_status_t knn_search_host_corpus(knn_handle_t h, const float *queries, int64_t m, const float *corpus_host,
+                                    int64_t n, int32_t d, int32_t k, int64_t part_rows, float *out_dist,
+                                    int32_t *out_idx, void *stream, const knn_options_t *opt);
+
+/*
  * knn_graph -- the k-NN graph of n points (Introduction: every corpus point is
  * also a query).  Same as knn_search(points, n, points, n, ...) except that each
  * point's own index is excluded; duplicates at distance 0 remain neighbours.

@@ -143,6 +143,30 @@ class Handle:
                                         self._stream(), ctypes.byref(o)))
         return dist, idx
 
+    def search_host_corpus(self, queries, corpus_host, k: int, part_rows=0, pivot="sample", precision="fp32",
+                           oversample=4, flags=0, metric="sqeuclidean"):
+        """search() with the corpus in host memory (a contiguous float32 CPU
+        tensor, pinned for copies that overlap the search), streamed to the
+        device in partitions of part_rows points (0: about 1 GiB)."""
+        torch = _torch()
+        if queries.dim() != 2 or queries.dtype != torch.float32 or not queries.is_cuda or not queries.is_contiguous():
+            raise ValueError("queries must be a contiguous 2-D float32 device tensor")
+        if (corpus_host.dim() != 2 or corpus_host.dtype != torch.float32 or corpus_host.is_cuda
+                or not corpus_host.is_contiguous()):
+            raise ValueError("corpus_host must be a contiguous 2-D float32 host tensor")
+        m, d = queries.shape
+        n, d2 = corpus_host.shape
+        if d != d2:
+            raise ValueError("queries and corpus differ in dimension")
+        dist = torch.empty((m, k), dtype=torch.float32, device=queries.device)
+        idx = torch.empty((m, k), dtype=torch.int32, device=queries.device)
+        o = self._opts(pivot, precision, oversample, flags, metric)
+        self._check(self.lib.knn_search_host_corpus(self.h, ctypes.c_void_p(queries.data_ptr()), m,
+                                                    ctypes.c_void_p(corpus_host.data_ptr()), n, d, k, int(part_rows),
+                                                    ctypes.c_void_p(dist.data_ptr()), ctypes.c_void_p(idx.data_ptr()),
+                                                    self._stream(), ctypes.byref(o)))
+        return dist, idx
+
     def batch_search(self, jobs, pivot="sample", precision="fp32", oversample=4, flags=0, out=None,
                      metric="sqeuclidean"):
         """Many independent k-NN problems in one call.  `jobs` is a list of

@@ -72,6 +72,7 @@ PROTOTYPES = {
     "knn_select_k_noalloc": (_ST, [_P, _P, _I64, _I64, _I64, _I32, _P, _P, _P, ctypes.POINTER(Options)]),
     "knn_partition": (_ST, [_P, _P, _I64, _I64, _I64, _P, _P, _P, _P, _P, _P]),
     "knn_search": (_ST, [_P, _P, _I64, _P, _I64, _I32, _I32, _P, _P, _P, ctypes.POINTER(Options)]),
+    "knn_search_host_corpus": (_ST, [_P, _P, _I64, _P, _I64, _I32, _I32, _I64, _P, _P, _P, ctypes.POINTER(Options)]),
     "knn_graph": (_ST, [_P, _P, _I64, _I32, _I32, _P, _P, _P, ctypes.POINTER(Options)]),
     "knn_batch_search": (_ST, [_P, ctypes.POINTER(Job), _I32, _P, ctypes.POINTER(Options)]),
     "knn_distances": (_ST, [_P, _P, _I64, _P, _I64, _I32, _P, _I64, _P]),

@@ -61,6 +61,9 @@ knn_status_t run_search(knn_handle_t h, const float *Q, int64_t m, const float *
 
 knn_status_t run_batch(knn_handle_t h, const knn_job_t *jobs, int32_t njobs, hipStream_t stream,
                        const knn_options_t *opt);
+knn_status_t run_search_host_corpus(knn_handle_t h, const float *Q, int64_t m, const float *C_host, int64_t n, int d,
+                                    int k, int64_t part_rows, float *out_dist, int32_t *out_idx, hipStream_t stream,
+                                    const knn_options_t *opt);
 void batch_release(knn_handle_t h);
 knn_status_t fail_msg(knn_handle_t h, knn_status_t s, const std::string &msg) { return fail(h, s, msg); }
 uint32_t *host_counter(knn_handle_t h) { return h->pinned; }
@@ -109,6 +112,12 @@ static knn_status_t ensure_buf(knn_handle_t h, void **buf, size_t *cap, size_t b
 knn_status_t ensure_ws(knn_handle_t h, size_t bytes, hipStream_t stream, void **out) {
     return ensure_buf(h, &h->ws, &h->ws_bytes, bytes, stream, out);
 }
+
+// The partition buffers and running results of knn_search_host_corpus.
+knn_status_t ensure_ooc_ws(knn_handle_t h, size_t bytes, hipStream_t stream, void **out) {
+    return ensure_buf(h, &h->ooc, &h->ooc_bytes, bytes, stream, out);
+}
+void set_host_rows(knn_handle_t h, int64_t rows) { h->host_rows = rows; }
 
 // The unit-vector copies of the cosine and Pearson distances (kept apart from
 // the general workspace, which the Euclidean path on them may regrow).
@@ -176,6 +185,10 @@ knn_status_t knn_destroy(knn_handle_t h) {
     batch_release(h);
     if (h->ws) hipFree(h->ws);
     if (h->uws) hipFree(h->uws);
+    if (h->ooc) hipFree(h->ooc);
+    for (hipEvent_t ev : h->ooc_ev)
+        if (ev) hipEventDestroy(ev);
+    if (h->copy_stream) hipStreamDestroy(h->copy_stream);
     if (h->stats_dev) hipFree(h->stats_dev);
     if (h->pinned) hipHostFree(h->pinned);
     for (void *p : {(void *)h->net_theta, (void *)h->net_theta_r, (void *)h->net_m, (void *)h->net_v,
@@ -354,6 +367,31 @@ knn_status_t knn_search(knn_handle_t h, const float *queries, int64_t m, const f
     hipSetDevice(h->device);
     if ((st = begin_stats(h, stream)) != KNN_SUCCESS) return st;
     return run_search(h, queries, m, corpus, n, d, k, false, out_dist, out_idx, stream, opt);
+}
+
+knn_status_t knn_search_host_corpus(knn_handle_t h, const float *queries, int64_t m, const float *corpus_host,
+                                    int64_t n, int32_t d, int32_t k, int64_t part_rows, float *out_dist,
+                                    int32_t *out_idx, void *stream_, const knn_options_t *opt) {
+    if (!h) return fail(nullptr, KNN_ERROR_INVALID_VALUE, "knn_search_host_corpus: handle is null");
+    if (m < 0) return fail(h, KNN_ERROR_INVALID_VALUE, "knn_search_host_corpus: m < 0");
+    knn_status_t st = check_points(h, "knn_search_host_corpus", corpus_host, n, d);
+    if (st != KNN_SUCCESS) return st;
+    if (k < 1) return fail(h, KNN_ERROR_INVALID_VALUE, "knn_search_host_corpus: k < 1");
+    if (k > n) return fail(h, KNN_ERROR_INVALID_VALUE, "knn_search_host_corpus: k > n");
+    if (k > kSelectMaxK) return fail(h, KNN_ERROR_UNSUPPORTED, "knn_search_host_corpus: k > 1024");
+    if (part_rows < 0) return fail(h, KNN_ERROR_INVALID_VALUE, "knn_search_host_corpus: part_rows < 0");
+    if ((st = check_options(h, "knn_search_host_corpus", opt)) != KNN_SUCCESS) return st;
+    if (m == 0) return KNN_SUCCESS;
+    if (!queries || !out_dist || !out_idx) return fail(h, KNN_ERROR_INVALID_VALUE, "knn_search_host_corpus: null pointer");
+    if (part_rows == 0) {
+        // partitions of about 1 GiB, never below k points
+        part_rows = (int64_t)((1ull << 30) / ((size_t)d * sizeof(float)));
+        if (part_rows < k) part_rows = k;
+    }
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    hipSetDevice(h->device);
+    if ((st = begin_stats(h, stream)) != KNN_SUCCESS) return st;
+    return run_search_host_corpus(h, queries, m, corpus_host, n, d, k, part_rows, out_dist, out_idx, stream, opt);
 }
 
 knn_status_t knn_graph(knn_handle_t h, const float *points, int64_t n, int32_t d, int32_t k, float *out_dist,

@@ -17,6 +17,10 @@ struct knn_handle_s {
     void *ws = nullptr;        // general workspace, grows on demand
     void *uws = nullptr;       // unit-vector copies (cosine / Pearson), grows on demand
     size_t uws_bytes = 0;
+    void *ooc = nullptr;       // host-corpus search: partition buffers and running results
+    size_t ooc_bytes = 0;
+    hipStream_t copy_stream = nullptr;       // host-to-device copies of corpus partitions
+    hipEvent_t ooc_ev[4] = {nullptr, nullptr, nullptr, nullptr};  // copied[2], freed[2]
     void *scratch = nullptr;   // device address of this device's static scratch array
     size_t ws_bytes = 0;
     unsigned long long *stats_dev = nullptr;  // kStatCount counters
