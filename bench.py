@@ -15,6 +15,16 @@ k = 64 (Gaussian mixture) with the distance product in BF16, 4x oversampled
 candidates and the exact FP32 re-rank; FP8 and FP32 products are timed once
 beside it, with recall against the FP64 oracle on 32 sampled rows.
 
+With --workload sweep: the paper's saturation shape, Q = 8 ... 256 rows of
+n = 2^20 uniform values, k = 32 and 1024, rows split across workgroups or not,
+with the nth_element CPU baseline beside it.
+
+With --workload select: knn_select_k on 16384 x 65536 squared distances, k =
+32, 256, 1024, every pivot rule, with the oracle and nth_element CPU baselines.
+
+With --workload hostcorpus: knn_search_host_corpus with an 8 GiB corpus in
+pinned host memory, its copies overlapping the search.
+
 With --workload batch the step is instead one knn_batch_search over 512
 uneven jobs (corpus sizes log-uniform in [1e3, 1e6], 1024 queries each, d in
 {64, 128, 768}, k log-uniform in [1, 1024], uniform or Gaussian-mixture data
@@ -49,7 +59,7 @@ def measured_traffic():
     import hashlib
     import re
     prof = os.path.join(ROOT, "profiles", "knng_fused_262144x1024_k32_traffic.md")
-    src = os.path.join(ROOT, "paper_1309_5478_amd", "csrc", "dist.hip")
+    src = os.path.join(ROOT, "paper_1309_5478_amd", "csrc", "gemm.hip")
     try:
         text = open(prof).read()
         want = re.search(r"source_sha256: ([0-9a-f]{64})", text).group(1)
@@ -103,7 +113,8 @@ def main():
     ap.add_argument("--no-select", action="store_true", help="skip the select_k block")
     ap.add_argument("--no-pivot-compare", action="store_true", help="skip the per-pivot-rule steps")
     ap.add_argument("--cpu-rows", type=int, default=1536, help="query rows in the CPU oracle sample (0: skip)")
-    ap.add_argument("--workload", default="knng", choices=["knng", "batch", "select", "lowprec"])
+    ap.add_argument("--no-bf16", action="store_true", help="skip the BF16-product row of the k-NNG workload")
+    ap.add_argument("--workload", default="knng", choices=["knng", "batch", "select", "lowprec", "sweep", "hostcorpus"])
     ap.add_argument("--batch-jobs", type=int, default=512)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference dispatch for memory counters)")
@@ -128,6 +139,10 @@ def main():
         return bench_select(args, knn, torch, np)
     if args.workload == "lowprec":
         return bench_lowprec(args, knn, torch, np, synth)
+    if args.workload == "sweep":
+        return bench_sweep(args, knn, torch, np, synth)
+    if args.workload == "hostcorpus":
+        return bench_hostcorpus(args, knn, torch, np, synth)
     N, d, k = args.n, args.d, args.k
     t0 = time.perf_counter()
     P = synth.gmm_points(N, d, seed=synth.SEEDS["knng_fused"])
@@ -185,6 +200,29 @@ def main():
             pivots[pv] = round(N / (time.perf_counter() - a), 1)
             log(f"knn_graph pivot={pv}: {pivots[pv]:.0f} rows/s")
 
+    # the same k-NN graph with the product in BF16 (k' = 4k candidates, exact
+    # FP32 re-rank), against the BF16 matrix-core peak
+    bf16 = None
+    if not args.no_bf16:
+        for _ in range(2):
+            out["bd"], out["bi"] = h.graph(dev, k, precision="bf16", flags=flags)
+            bst = h.stats()
+        a = time.perf_counter()
+        bsteps = 2
+        bms = bfl = 0.0
+        for _ in range(bsteps):
+            out["bd"], out["bi"] = h.graph(dev, k, precision="bf16", flags=flags)
+            bst = h.stats()
+            bms += bst["product_ms"]
+            bfl += bst["product_flops"]
+        bsec = (time.perf_counter() - a) / bsteps
+        btf = bfl / (bms / 1e3) / 1e12 if bms > 0 else 0.0
+        bf16 = {"ms_per_step": round(bsec * 1e3, 2), "rows_per_s": round(N / bsec, 1),
+                "product_ms_per_launch": round(bms / max(bsteps * bst["product_launches"], 1), 3),
+                "product_tflops": round(btf, 1), "frac_of_bf16_peak": round(btf / PEAK_MFMA_TFLOPS["bf16"], 4),
+                "rows_uncertified": bst["rows_uncertified"], "fallback_rows": bst["fallback_rows"]}
+        log(f"knn_graph bf16: {bf16['ms_per_step']} ms/step, {bf16['rows_per_s']:.0f} rows/s; product {btf:.1f} TFLOP/s")
+
     select = None
     if not args.no_select:
         R = min(args.select_rows, N)
@@ -224,6 +262,20 @@ def main():
         parity = parity_block(P, P, rows, g_dist[rows], g_idx[rows], od, oi, k, self_ids=rows)
         parity["rows_uncertified"] = uncert // max(args.steps, 1)
         log(f"parity: {parity}")
+        if bf16 is not None:
+            bd, bi = out["bd"].cpu().numpy()[rows], out["bi"].cpu().numpy()[rows]
+            hits = sum(len(set(x.tolist()) & set(y[:k].tolist())) for x, y in zip(bi, oi))
+            bf16["recall"] = round(hits / (len(rows) * k), 6)
+            bf16["parity"] = parity_block(P, P, rows, bd, bi, od, oi, k, self_ids=rows)
+            log(f"bf16 recall {bf16['recall']}, parity {bf16['parity']}")
+        # one core: a smaller sample of the same rows
+        r1 = rows[:64]
+        a = time.perf_counter()
+        oracle.knn(P[r1], P, k + 1, self_ids=r1, nthreads=1)
+        sec1 = time.perf_counter() - a
+        cpu["one_core"] = {"value": round(len(r1) / sec1, 3), "unit": "rows/s", "cores": 1,
+                           "sample": f"{len(r1)} of the same rows on one thread, {sec1:.1f} s"}
+        log(f"oracle one core: {cpu['one_core']['value']} rows/s")
 
     line = {
         "metric": METRIC,
@@ -241,6 +293,7 @@ def main():
         "config": {"workload": f"fused k-NNG, N={N}, d={d}, k={k}, Gaussian mixture (64 comp.), FP32",
                    "N": N, "d": d, "k": k, "pivot": args.pivot, "oversample": 4},
         "pivots_rows_per_s": pivots,
+        "bf16": bf16,
         "roofline": {"bound": "mfma", "kernel": "dist_gemm_kernel (fused filter epilogue)",
                      "achieved": round(achieved, 2), "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4),
@@ -304,6 +357,24 @@ def bench_select(args, knn, torch, np):
         cpu = {"value": round(3 * len(rows) * 4 * N / sec / 1e9, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
                "sample": f"{len(rows)} rows of the matrix at each of k = 32, 256, 1024 (stable sort of each row), {sec:.1f} s"}
         log(f"oracle: {cpu['value']} GB/s on {threads} threads")
+        # one core, and the standard library's nth_element + sort of the first k
+        # (the kind of CPU selection the paper compares against), on the same rows
+        a = time.perf_counter()
+        oracle.select_k(D[rows[:64]], 1024, nthreads=1)
+        s1 = time.perf_counter() - a
+        cpu["one_core"] = {"value": round(64 * 4 * N / s1 / 1e9, 3), "unit": "GB/s", "cores": 1,
+                           "sample": f"64 of the rows at k = 1024 on one thread, {s1:.1f} s"}
+        nth = {}
+        for k in (32, 256, 1024):
+            for nt, tag in ((threads, "all_cores"), (1, "one_core")):
+                rr = rows if nt > 1 else rows[:64]
+                a = time.perf_counter()
+                oracle.nth_select_k(D[rr], k, nthreads=nt)
+                sec_n = time.perf_counter() - a
+                nth[f"k={k},{tag}"] = round(len(rr) * 4 * N / sec_n / 1e9, 3)
+        cpu["nth_element_GBps"] = nth
+        cpu["nth_element_cores"] = threads
+        log(f"oracle one core: {cpu['one_core']['value']} GB/s; nth_element GB/s: {nth}")
     line = {
         "metric": "select_k GB/s (16384x65536 FP32 squared distances, k = 32 / 256 / 1024)",
         "value": round(gbs, 1),
@@ -323,6 +394,162 @@ def bench_select(args, knn, torch, np):
         "per_k": res,
         "roofline": {"bound": "hbm", "kernel": "select_rows_kernel", "achieved": round(gbs, 1),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_sweep(args, knn, torch, np, synth):
+    """The paper's saturation workload shape (Results, Figure 8): rows of
+    n = 2^20 uniform[0,1) values, Q = 8 ... 256 rows, k = 32 and 1024, with
+    rows split across workgroups (default) and without (one workgroup per row,
+    as the paper's method); time per row and GB/s.  Beside it the CPU selection
+    baseline (nth_element + sort of k) at Q = 256, one core and all cores."""
+    n = 1 << 20
+    Qmax = 256
+    D = synth.uniform_points(Qmax, n, seed=synth.SEEDS["sweep"])
+    dev = torch.from_numpy(D).cuda()
+    torch.cuda.synchronize()
+    h = knn.Handle(0)
+    res = {}
+    for k in (32, 1024):
+        for Q in (8, 16, 32, 64, 128, 256):
+            sub = dev[:Q]
+            for tag, flags in (("split", 0), ("whole_rows", knn.FLAG_NO_SPLIT)):
+                for _ in range(max(args.warmup, 1)):
+                    h.select_k(sub, k, flags=flags)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(args.steps):
+                    h.select_k(sub, k, flags=flags)
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / args.steps
+                parts = h.stats()["split_parts"]
+                nbytes = 4 * Q * n + 8 * Q * k
+                res[f"k={k},Q={Q},{tag}"] = {"ms": round(ms, 4), "us_per_row": round(1e3 * ms / Q, 2),
+                                              "GB/s": round(nbytes / ms / 1e6, 1), "parts": parts}
+                log(f"sweep k={k} Q={Q} {tag}: {ms:.3f} ms, {1e3 * ms / Q:.2f} us/row, {nbytes / ms / 1e6:.0f} GB/s,"
+                    f" parts {parts}")
+    cpu = None
+    if args.cpu_rows > 0:
+        import oracle
+        threads = oracle.default_threads()
+        nth = {}
+        for k in (32, 1024):
+            for nt, tag, Q in ((threads, "all_cores", 256), (1, "one_core", 32)):
+                a = time.perf_counter()
+                oracle.nth_select_k(D[:Q], k, nthreads=nt)
+                sec = time.perf_counter() - a
+                nth[f"k={k},{tag}"] = {"us_per_row": round(1e6 * sec / Q, 1), "rows": Q}
+        cpu = {"value": nth["k=1024,one_core"]["us_per_row"], "unit": "us/row", "cores": 1, "kind": "nth_element",
+               "sample": "std::nth_element + sort of the first k per row: 32 rows on one core, 256 rows on all"
+                         f" {threads} cores, k = 32 and 1024", "per_case": nth}
+        log(f"nth_element: {nth}")
+    head = res["k=32,Q=8,split"]
+    line = {
+        "metric": "select_k rows of n = 2^20 at few rows (saturation sweep, Q = 8 ... 256)",
+        "value": head["GB/s"],
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms"],
+        "higher_is_better": True,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "select_k on Q x 2^20 uniform[0,1) FP32 rows, Q = 8 ... 256, k = 32 and 1024;"
+                               " value: Q = 8, k = 32, rows split across workgroups", "n": n},
+        "per_case": res,
+        "roofline": {"bound": "hbm", "kernel": "select_rows_kernel (parts) + key-list merges",
+                     "achieved": head["GB/s"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(head["GB/s"] / PEAK_HBM_GBS, 4), "traffic": None},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_hostcorpus(args, knn, torch, np, synth):
+    """A corpus in pinned host memory (2^23 points in d = 256, 8 GiB, Gaussian
+    mixture) searched by 16384 resident queries, k = 32, in 1 GiB partitions
+    whose copies overlap the search (knn_search_host_corpus).  Beside it: the
+    copies alone and the search of one resident partition, to show the overlap."""
+    n, d, m, k = 1 << 23, 256, 16384, 32
+    t0 = time.perf_counter()
+    C = synth.gmm_points(n, d, seed=synth.SEEDS["lowprec"] + 10)
+    Q = synth.gmm_points(m, d, seed=synth.SEEDS["lowprec"] + 11)
+    Cp = torch.empty((n, d), dtype=torch.float32, pin_memory=True)
+    Cp.copy_(torch.from_numpy(C))
+    qd = torch.from_numpy(Q).cuda()
+    log(f"generated {n}x{d} host corpus ({n * d * 4 / 2**30:.0f} GiB, pinned) in {time.perf_counter() - t0:.1f} s")
+    h = knn.Handle(0)
+    part = (1 << 30) // (d * 4)
+    for _ in range(max(args.warmup, 1)):
+        h.search_host_corpus(qd, Cp, k, part_rows=part)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        gd, gi = h.search_host_corpus(qd, Cp, k, part_rows=part)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t) / args.steps
+    # the copies alone, and the search of one resident partition
+    dbuf = torch.empty((part, d), dtype=torch.float32, device="cuda")
+    t = time.perf_counter()
+    for p0 in range(0, n, part):
+        dbuf[: min(part, n - p0)].copy_(Cp[p0:p0 + part], non_blocking=True)
+    torch.cuda.synchronize()
+    copy_sec = time.perf_counter() - t
+    h.search(qd, dbuf, k)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    h.search(qd, dbuf, k)
+    torch.cuda.synchronize()
+    part_sec = time.perf_counter() - t
+    parts = (n + part - 1) // part
+    serial = copy_sec + parts * part_sec
+    log(f"host corpus: {sec * 1e3:.1f} ms/step; copies alone {copy_sec * 1e3:.1f} ms "
+        f"({n * d * 4 / copy_sec / 1e9:.1f} GB/s), {parts} partition searches {parts * part_sec * 1e3:.1f} ms")
+    cpu = None
+    if args.cpu_rows > 0:
+        import oracle
+        threads = oracle.default_threads()
+        rows = np.arange(0, m, m // 16)
+        a = time.perf_counter()
+        od, oi = oracle.knn(Q[rows], C, k, nthreads=threads)
+        csec = time.perf_counter() - a
+        g = gi.cpu().numpy()[rows]
+        match = int(sum(set(x.tolist()) == set(y.tolist()) for x, y in zip(g, oi)))
+        cpu = {"value": round(len(rows) / csec, 3), "unit": "queries/s", "cores": threads, "kind": "oracle",
+               "sample": f"{len(rows)} queries against the whole corpus (FP64 direct distances + stable sort),"
+                         f" {csec:.1f} s; {match} of {len(rows)} neighbour sets equal to the GPU's"}
+        log(f"oracle: {cpu['value']} queries/s; sets equal on {match}/{len(rows)} rows")
+    flops = 2.0 * m * n * d
+    line = {
+        "metric": "k-NN queries/s with the corpus in host memory (2^23 x 256 corpus, 16384 queries, k = 32)",
+        "value": round(m / sec, 1),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(sec * 1e3, 2),
+        "higher_is_better": True,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "knn_search_host_corpus: 8 GiB pinned host corpus (Gaussian mixture, d = 256),"
+                               " 16384 resident queries, k = 32, 1 GiB partitions", "n": n, "d": d, "m": m, "k": k},
+        "copy_only_ms": round(copy_sec * 1e3, 1),
+        "h2d_GBps": round(n * d * 4 / copy_sec / 1e9, 1),
+        "partition_search_ms": round(part_sec * 1e3, 1),
+        "serial_estimate_ms": round(serial * 1e3, 1),
+        "overlap_saving": round(1.0 - sec / serial, 3),
+        "roofline": {"bound": "mfma", "kernel": "dist_gemm_kernel (fused filter epilogue, per partition)",
+                     "achieved": round(flops / sec / 1e12, 1), "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(flops / sec / 1e12 / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": None},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
@@ -444,6 +671,20 @@ def bench_batch(args, knn, torch, np):
     log(f"knn_batch_search: {ms_per_step:.1f} ms/step, {queries / ms_per_step * 1e3:.0f} queries/s;"
         f" grouped product {prod_ms:.2f} ms, {achieved:.1f} TFLOP/s")
 
+    # the same call with every step eager (no graph replays), and with the
+    # plain pivot rule instead of the learned one (its own plan and graphs)
+    compare = {}
+    for tag, extra, pv in (("eager", knn.FLAG_NO_GRAPH, pivot), ("plain_pivots", 0, "plain"),
+                           ("sample_pivots", 0, "sample")):
+        h.batch_search(jobs, pivot=pv, flags=flags | extra, out=outs)
+        h.stats()
+        a = time.perf_counter()
+        h.batch_search(jobs, pivot=pv, flags=flags | extra, out=outs)
+        h.stats()
+        compare[tag] = round((time.perf_counter() - a) * 1e3, 2)
+        log(f"knn_batch_search {tag}: {compare[tag]} ms")
+    compare["graph_learned"] = round(ms_per_step, 2)
+
     cpu = None
     if args.cpu_rows > 0:
         import oracle
@@ -486,6 +727,7 @@ def bench_batch(args, knn, torch, np):
                      "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": None,
                      "launch_ms": round(prod_ms, 3), "flops_per_launch": flops},
         "fallback_rows_per_step": fallback / max(args.steps, 1),
+        "ms_per_call": compare,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
