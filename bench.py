@@ -118,6 +118,10 @@ def main():
     ap.add_argument("--batch-jobs", type=int, default=512)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference dispatch for memory counters)")
+    ap.add_argument("--select-case", default=None,
+                    help="select workload: only this case, as k,pivot (e.g. 1024,sample), one timed call per step")
+    ap.add_argument("--precisions", default="bf16,fp8,fp32",
+                    help="lowprec workload: the timed precision first, then the others (comma-separated)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -133,6 +137,12 @@ def main():
     import synth
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)           # reads and writes exactly 1 GiB
+        torch.cuda.synchronize()
+        del src, dst
     if args.workload == "batch":
         return bench_batch(args, knn, torch, np)
     if args.workload == "select":
@@ -151,12 +161,6 @@ def main():
     torch.cuda.synchronize()
     h = knn.Handle(0)
     flags = knn.FLAG_TIMING
-    if args.calibrate_copy:
-        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)           # reads and writes exactly 1 GiB
-        torch.cuda.synchronize()
-        del src, dst
 
     out = {}
 
@@ -322,27 +326,30 @@ def bench_select(args, knn, torch, np):
     torch.cuda.synchronize()
     h = knn.Handle(0)
     res, tot_bytes, tot_ms = {}, 0.0, 0.0
-    for k in (32, 256, 1024):
+    cases = [(k, pv) for k in (32, 256, 1024) for pv in ("sample", "learned", "plain")]
+    if args.select_case:
+        ck, cp = args.select_case.split(",")
+        cases = [(int(ck), cp)]
+    for k, pivot in cases:
         nbytes = 4 * M * N + 8 * M * k
-        for pivot in ("sample", "learned", "plain"):
-            for _ in range(args.warmup):
-                h.select_k(dev, k, pivot=pivot)
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(args.steps):
-                h.select_k(dev, k, pivot=pivot)
-            e1.record()
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / args.steps
-            st = h.stats()
-            res[f"k={k},{pivot}"] = {"ms": round(ms, 4), "GB/s": round(nbytes / ms / 1e6, 1),
-                                     "passes_per_row": round(st["passes_total"] / M, 3),
-                                     "streams_per_row": round(st["stream_passes_total"] / M, 4)}
-            log(f"select_k k={k} pivot={pivot}: {ms:.3f} ms, {nbytes / ms / 1e6:.0f} GB/s")
-            if pivot == "sample":
-                tot_bytes += nbytes
-                tot_ms += ms
+        for _ in range(args.warmup):
+            h.select_k(dev, k, pivot=pivot)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            h.select_k(dev, k, pivot=pivot)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        st = h.stats()
+        res[f"k={k},{pivot}"] = {"ms": round(ms, 4), "GB/s": round(nbytes / ms / 1e6, 1),
+                                 "passes_per_row": round(st["passes_total"] / M, 3),
+                                 "streams_per_row": round(st["stream_passes_total"] / M, 4)}
+        log(f"select_k k={k} pivot={pivot}: {ms:.3f} ms, {nbytes / ms / 1e6:.0f} GB/s")
+        if pivot == "sample" or args.select_case:
+            tot_bytes += nbytes
+            tot_ms += ms
     gbs = tot_bytes / tot_ms / 1e6
     cpu = None
     if args.cpu_rows > 0:
@@ -596,8 +603,9 @@ def bench_lowprec(args, knn, torch, np, synth):
             f" ({100 * r['frac_of_peak']:.1f} % of peak), recall {recall}, max rel. distance error {rel:.2e}")
         return r, tot
 
-    res, tot = run("bf16", args.steps, args.warmup)
-    others = {p: run(p, 1, 1)[0] for p in ("fp8", "fp32")}
+    precs = args.precisions.split(",")
+    res, tot = run(precs[0], args.steps, args.warmup)
+    others = {p: run(p, 1, 1)[0] for p in precs[1:]}
     achieved = res["product_tflops"]
     line = {
         "metric": "reduced-precision k-NNG rows/s (N=2^20, d=256, k=64, BF16 product + FP32 re-rank)",
@@ -615,9 +623,8 @@ def bench_lowprec(args, knn, torch, np, synth):
         "config": {"workload": f"reduced-precision k-NNG, N={N}, d={d}, k={k}, Gaussian mixture (64 comp.),"
                                " BF16 product, k' = 4k candidates, exact FP32 re-rank",
                    "N": N, "d": d, "k": k, "oversample": 4},
-        "bf16": res,
-        "fp8": others["fp8"],
-        "fp32": others["fp32"],
+        precs[0]: res,
+        **others,
         "roofline": {"bound": "mfma", "kernel": "dist_gemm_kernel (fused filter epilogue, BF16)",
                      "achieved": achieved, "peak": PEAK_MFMA_TFLOPS["bf16"], "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_MFMA_TFLOPS["bf16"], 4), "traffic": None,

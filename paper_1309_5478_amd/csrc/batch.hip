@@ -550,6 +550,30 @@ hipError_t enqueue_final(const BatchState &b, knn_handle_t h, int num_cu, hipStr
                           hipMemcpyDeviceToHost, s);
 }
 
+// After the flagged rows' candidate lists are re-done: the candidate selection,
+// certificate and re-rank of one part again (its uncertified list restarts).
+hipError_t refinal_part(const BatchState &b, knn_handle_t h, int num_cu, size_t pi, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    const BatchPart &pt = b.parts[pi];
+    const Plan &p = b.jobs[pt.job].p;
+    BTRY(launch_fill_u32(b.sh.nu + pi, 1, 0u, s));
+    SelectArgs ka{};
+    ka.keys = pt.cand;
+    ka.key_cnt = pt.cnt;
+    ka.rows = pt.mb;
+    ka.cols = (uint32_t)p.cap;
+    ka.ld = p.cap;
+    ka.k = (uint32_t)p.kk;
+    ka.out_val = pt.sv;
+    ka.out_idx = pt.si;
+    ka.mode = b.smode;
+    ka.net = b.smode == kPivotLearned ? b.net : nullptr;
+    BTRY(launch_select_keys(ka, b.sh.selws, pt.mb, num_cu, s));
+    BTRY(certify_rerank(b, h, pi, pt.sv, pt.si, s));
+    return hipMemcpyAsync(b.nflag_host + b.parts.size() + pi, b.sh.nu + pi, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                          s);
+}
+
 // Exact re-do of the flagged rows of every part (after the flag counts reached
 // the host), as in knn_search.
 hipError_t run_fallback(const BatchState &b, int num_cu, hipStream_t s, int64_t *total) {
@@ -993,12 +1017,11 @@ knn_status_t run_batch(knn_handle_t h, const knn_job_t *jobs, int32_t njobs, hip
     for (size_t pi = 0; pi < b.parts.size(); ++pi) fallback += b.nflag_host[pi];
     if (fallback > 0) {
         // rare: the flagged rows' candidate lists are re-done exactly, then the
-        // selection, certificate and re-rank of the filtered parts run again
+        // selection, certificate and re-rank of the parts holding them run again
         int64_t done = 0;
         KTRY(run_fallback(b, num_cu, stream, &done));
         for (size_t pi = 0; pi < b.parts.size(); ++pi)
-            if (!b.parts[pi].direct) KTRY(launch_fill_u32(b.sh.nu + pi, 1, 0u, stream));
-        KTRY(enqueue_final(b, h, num_cu, stream));
+            if (b.nflag_host[pi] > 0) KTRY(refinal_part(b, h, num_cu, pi, stream));
         KTRY(hipStreamSynchronize(stream));
     }
     int64_t rerun = 0;
