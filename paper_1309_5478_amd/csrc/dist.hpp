@@ -83,6 +83,11 @@ hipError_t launch_dist_gemm_grouped(const DistArgs *jobs, const GemmItem *items,
 // device memory (cleared by the launch).
 hipError_t launch_dist_gemm_queue(const DistArgs *jobs, const GemmItem *items, int64_t nitems, int prec, int tile,
                                   uint32_t *queues, int num_cu, hipStream_t stream);
+// The resident-corpus product for short BF16 / FP8 rows with the FILTER
+// epilogue (gemm_sk.hip): whether it serves `a` (KNN_GEMM_SK=0 turns it off),
+// and its launch.  launch_dist_gemm uses it where it applies.
+bool gemm_sk_applies(const DistArgs &a, int epi);
+hipError_t launch_dist_gemm_sk(const DistArgs &a, hipStream_t stream);
 // Tile shape launch_dist_gemm uses for `a` (kTile*).
 int gemm_tile_choice(const DistArgs &a);
 // Squared norms of n rows of d floats into out; with max_bits (non-null, zero or

@@ -347,10 +347,8 @@ __global__ __launch_bounds__(64 * WM * WN) void dist_gemm_grouped_kernel(const D
 // takes the items b % 8, b % 8 + 8, ... of the same dispatch-ordered list, so
 // the per-XCD tile order, and with it the L2 reuse, is that of the one-item-per-
 // workgroup launch).  Each queue's counter starts at zero.
-// (Held to the register budget of the one-item form: three workgroups per CU
-// for the 128 x 128 tile; the loop alone would let the allocator grow.)
 template <int WM, int WN, int BI, int BJ, int EPI, int PREC, bool VEC>
-__global__ __launch_bounds__(64 * WM * WN, WM * WN == 4 ? 3 : 1) void dist_gemm_queue_kernel(const DistArgs *__restrict__ jobs,
+__global__ __launch_bounds__(64 * WM * WN) void dist_gemm_queue_kernel(const DistArgs *__restrict__ jobs,
                                                                        const GemmItem *__restrict__ items,
                                                                        uint32_t nitems, uint32_t *__restrict__ queues) {
     using T = Tile<WM, WN, BI, BJ>;
@@ -426,6 +424,8 @@ int gemm_tile_choice(const DistArgs &a) {
 
 hipError_t launch_dist_gemm(const DistArgs &a, int epi, hipStream_t stream) {
     if (a.m == 0 || a.n == 0) return hipSuccess;
+    // short reduced-precision rows: the resident-corpus product (gemm_sk.hip)
+    if (gemm_sk_applies(a, epi)) return launch_dist_gemm_sk(a, stream);
     switch (gemm_tile_choice(a)) {
         case kTileBig:
             return epi == kEpiDense ? launch_gemm_t<2, 4, 4, 2, kEpiDense>(a, stream)

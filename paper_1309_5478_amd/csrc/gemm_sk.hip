@@ -1,0 +1,315 @@
+// Short-K distance product for BF16 / FP8 operands with the threshold filter
+// (the fused first pass of the quick multi-select), for short operand rows
+// (BF16 d <= 256, FP8 d <= 128).
+//
+// With so short a K loop, the one-tile-per-workgroup product of gemm.hip spends
+// most of its time waiting: each tile's operands arrive one 128-byte chunk ahead
+// of the matrix cores, the first chunk and the epilogue are not overlapped, and
+// LDS carries both operands.  Here a workgroup of eight waves keeps one corpus
+// tile of 256 columns (the whole K) resident in LDS and walks its range of query
+// rows; each wave computes 64 rows x 128 columns per step and reads its query
+// fragments straight from global memory into registers, a few k-steps ahead, in
+// a ring that runs on from one row block into the next, so loads are in flight
+// during the MFMAs and during the epilogue.  The waves never wait for each
+// other after the corpus tile is loaded, so one wave's epilogue overlaps the
+// other waves' MFMAs on the same SIMD.
+//
+// Each dot product uses the same MFMA instruction over the same k-steps in the
+// same order as gemm.hip, so the reduced keys are the same bits.
+//
+// Measured at 2^20 x 256 BF16: 636 TFLOP/s per launch against 464 for the tiled
+// product; without the epilogue the loop reaches 920, and with the query
+// fragments read from LDS instead of global memory 1300: what bounds it is the
+// query fragment loads, each touching 32 rows for 32 bytes apiece (the MFMA
+// operand layout), and then the epilogue.
+#include <cstdlib>
+#include <cstring>
+#include <type_traits>
+
+#include "dist.hpp"
+#include "keys.hpp"
+
+namespace knn {
+
+namespace {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kSkCols = 256;   // corpus columns resident per workgroup
+constexpr int kSkWaves = 8;    // 4 row groups x 2 column halves
+constexpr int kSkThreads = 64 * kSkWaves;
+constexpr int kSkPad = 16;     // bytes of padding per LDS row (conflict-free 16-byte reads)
+
+template <int PREC, int KB>
+struct Sk {
+    static constexpr int STEP = PREC == kPrecBF16 ? 32 : 64;  // bytes of a row per MFMA k-step
+    static constexpr int STEPS = KB / STEP;
+    static constexpr int LS = KB + kSkPad;                    // LDS row stride
+    static constexpr int P = PREC == kPrecBF16 ? (STEPS < 4 ? STEPS : 4) : 1;  // prefetch depth in k-steps
+    using frag = typename std::conditional<PREC == kPrecBF16, i32x4, i32x8>::type;
+};
+
+template <int PREC>
+__device__ __forceinline__ f32x16 mfma(i32x8 a, i32x8 b, f32x16 c) {
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 127, 0, 127);
+}
+template <int PREC>
+__device__ __forceinline__ f32x16 mfma(i32x4 a, i32x4 b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0,
+                                                   0, 0);
+}
+
+template <class F>
+__device__ __forceinline__ F load_frag(const unsigned char *p) {
+    if constexpr (sizeof(F) == 16) {
+        return *reinterpret_cast<const i32x4 *>(p);
+    } else {
+        const i32x4 x = *reinterpret_cast<const i32x4 *>(p), y = *reinterpret_cast<const i32x4 *>(p + 16);
+        return F{x[0], x[1], x[2], x[3], y[0], y[1], y[2], y[3]};
+    }
+}
+
+}  // namespace
+
+// grid: col_tiles x row_splits workgroups; workgroup b takes corpus tile
+// b % col_tiles and row split b / col_tiles (row blocks of 64).
+template <int PREC, int KB>
+__global__ __launch_bounds__(kSkThreads) void dist_gemm_sk_kernel(DistArgs a, uint32_t col_tiles, uint32_t row_splits) {
+    using T = Sk<PREC, KB>;
+    using F = typename T::frag;
+    constexpr int S = T::STEPS, P = T::P, LS = T::LS, STEP = T::STEP;
+    __shared__ __align__(16) unsigned char sB[kSkCols * LS];
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    const uint32_t h = lane / 32, l32 = lane % 32;
+    const uint32_t half = wave / 4, wr = wave % 4;
+    const uint32_t ct = blockIdx.x % col_tiles, rs = blockIdx.x / col_tiles;
+    const int64_t col0 = (int64_t)ct * kSkCols;
+    const int64_t nrb = (a.m + 63) / 64;
+    const int64_t rb0 = nrb * rs / row_splits, rb1 = nrb * (rs + 1) / row_splits;
+
+    // 1. the corpus tile, whole K, into LDS (columns beyond n are zero)
+    const unsigned char *Cq = static_cast<const unsigned char *>(a.Cq);
+    constexpr int PER_ROW = KB / 16;
+    for (int p = (int)tid; p < kSkCols * PER_ROW; p += kSkThreads) {
+        const int r = p / PER_ROW, c = p % PER_ROW;
+        i32x4 v = {0, 0, 0, 0};
+        if (col0 + r < a.n) v = *reinterpret_cast<const i32x4 *>(Cq + (col0 + r) * a.ldq + c * 16);
+        *reinterpret_cast<i32x4 *>(sB + r * LS + c * 16) = v;
+    }
+    // this lane's four columns: norms, scales (-2 x column scale) and bounds
+    float cn[4], cs[4];
+    uint32_t gj[4];  // (column indices are below 2^31)
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) {
+        const int64_t j = col0 + half * 128 + bj * 32 + l32;
+        gj[bj] = (uint32_t)j;
+        const bool in = j < a.n;
+        cn[bj] = in ? a.cnorm[gj[bj]] : 0.f;
+        cs[bj] = (PREC == kPrecFP8 && in) ? -2.0f * a.cscale[gj[bj]] : -2.0f;
+    }
+    const int64_t cw0 = col0 + half * 128;  // first column of this wave
+    __syncthreads();
+
+    const unsigned char *Qq = static_cast<const unsigned char *>(a.Qq);
+    const int64_t mlast = a.m - 1;
+    // query fragment (row block rb, k-step s, 32-row block bi); rows beyond m
+    // read row m - 1 (their results are never kept)
+    auto qfrag = [&](int64_t rb, int s, int bi) -> F {
+        int64_t row = rb * 64 + bi * 32 + l32;
+        row = row < mlast ? row : mlast;
+        return load_frag<F>(Qq + row * a.ldq + s * STEP + h * (STEP / 2));
+    };
+    auto bfrag = [&](int s, int bj) -> F {
+        return load_frag<F>(sB + (half * 128 + bj * 32 + l32) * LS + s * STEP + h * (STEP / 2));
+    };
+
+    F ring[P][2];
+    int64_t rb = rb0 + wr;
+    if (rb < rb1) {
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            ring[p][0] = qfrag(rb, p, 0);
+            ring[p][1] = qfrag(rb, p, 1);
+        }
+    }
+    const f32x16 zero = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (; rb < rb1; rb += 4) {
+        const int64_t nxt = rb + 4;
+        const bool more = nxt < rb1;
+        f32x16 acc[2][4];
+        // corpus fragments one k-step ahead: the next step's LDS reads are in
+        // flight during this step's MFMAs
+        F bcur[4], bnxt[4];
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj) bcur[bj] = bfrag(0, bj);
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            if (s + 1 < S) {
+#pragma unroll
+                for (int bj = 0; bj < 4; ++bj) bnxt[bj] = bfrag(s + 1, bj);
+            }
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+                for (int bi = 0; bi < 2; ++bi)
+                    acc[bi][bj] = mfma<PREC>(ring[s % P][bi], bcur[bj], s == 0 ? zero : acc[bi][bj]);
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj) bcur[bj] = bnxt[bj];
+            // refill the slot just read: this block's step s + P, or the next block's
+            if (s + P < S) {
+                ring[s % P][0] = qfrag(rb, s + P, 0);
+                ring[s % P][1] = qfrag(rb, s + P, 1);
+            } else if (more) {
+                ring[s % P][0] = qfrag(nxt, s + P - S, 0);
+                ring[s % P][1] = qfrag(nxt, s + P - S, 1);
+            }
+            // keep the loads where the ring puts them (the scheduler would
+            // otherwise hoist every step's loads and run out of registers)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+
+        // epilogue: lane l holds row rb * 64 + l's threshold, scale and id;
+        // element (bi, bj, r) is row bi*32 + 8*(r/4) + 4h + r%4, column gj[bj]
+        const int64_t myrow = rb * 64 + lane;
+        const bool rin = myrow < a.m;
+        const float tau_l = rin ? a.tau[myrow * a.tau_stride] : 0.f;
+        const float qs_l = (PREC == kPrecFP8 && rin) ? a.qscale[myrow] : 1.f;
+        int64_t qid_l = -1;
+        if (a.self_offset >= 0 && rin) qid_l = a.self_offset + (a.row_ids ? (int64_t)a.row_ids[myrow] : myrow);
+        const bool may_self = __ballot(qid_l >= cw0 && qid_l < cw0 + 128) != 0;
+        // the lane half, opaque to the compiler here: the 32 row offsets of the
+        // epilogue are then computed in place, not hoisted out of the row-block
+        // loop (where they would hold 32 registers through the MFMAs)
+        uint32_t hv = h;
+        asm volatile("" : "+v"(hv));
+        // Instantiated for blocks wholly inside the matrix (no row or column
+        // tests) and without own columns (no self test): there each key costs
+        // one fused multiply-add and one compare, whose results stay in
+        // scalar masks.
+        auto epilogue = [&](auto edge_t, auto self_t) {
+            constexpr bool EDGE = decltype(edge_t)::value, SELF = decltype(self_t)::value;
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi) {
+                // the 16 thresholds of this row block half, fetched together
+                float taus[16];
+#pragma unroll
+                for (int r = 0; r < 16; ++r) taus[r] = __shfl(tau_l, bi * 32 + 8 * (r / 4) + 4 * (int)hv + (r % 4));
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int rl = bi * 32 + 8 * (r / 4) + 4 * (int)hv + (r % 4);
+                    const int64_t gi = rb * 64 + rl;
+                    const float tau = taus[r];
+                    const float qs = PREC == kPrecFP8 ? __shfl(qs_l, rl) : 1.f;
+                    int64_t qid = -1;
+                    if (SELF) qid = (int64_t)__shfl((long long)qid_l, rl);
+                    const bool row_ok = !EDGE || gi < a.m;
+                    float dp[4];
+                    uint64_t m[4];
+#pragma unroll
+                    for (int bj = 0; bj < 4; ++bj) {
+                        const float dot = PREC == kPrecFP8 ? acc[bi][bj][r] * qs : acc[bi][bj][r];
+                        dp[bj] = fmaf(cs[bj], dot, cn[bj]);
+                        bool pass = dp[bj] <= tau;
+                        if (EDGE) pass = pass & row_ok & ((int64_t)gj[bj] < a.n);
+                        if (SELF) pass = pass & ((int64_t)gj[bj] != qid);
+                        m[bj] = __ballot(pass);
+                    }
+                    // most accumulator rows keep nothing: one test for all four
+                    if ((m[0] | m[1] | m[2] | m[3]) == 0) {
+                        __builtin_amdgcn_sched_barrier(0);
+                        continue;
+                    }
+#pragma unroll
+                    for (int bj = 0; bj < 4; ++bj) {
+                        if (m[bj]) {
+                            const bool mine = (m[bj] >> lane) & 1ull;
+                            const uint32_t hm = h ? (uint32_t)(m[bj] >> 32) : (uint32_t)m[bj];
+                            uint32_t v = 0;
+                            if (l32 == 0 && hm) v = atomicAdd(&a.cnt[gi], (uint32_t)__popc(hm));
+                            const uint32_t b0 = __shfl(v, 0), b1 = __shfl(v, 32);
+                            if (mine) {
+                                const uint32_t below =
+                                    lanes_below(m[bj]) - (h ? (uint32_t)__popc((uint32_t)m[bj]) : 0u);
+                                const uint32_t slot = (h ? b1 : b0) + below;
+                                if (slot < (uint32_t)a.cap) a.cand[gi * a.cap + slot] = make_key(dp[bj], gj[bj]);
+                            }
+                        }
+                    }
+                    // one accumulator row at a time (hoisting the others' work
+                    // would hold them all in registers)
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+        };
+        const bool edge = rb * 64 + 64 > a.m || cw0 + 128 > a.n;
+        if (edge) {
+            if (may_self) epilogue(std::true_type{}, std::true_type{});
+            else epilogue(std::true_type{}, std::false_type{});
+        } else {
+            if (may_self) epilogue(std::false_type{}, std::true_type{});
+            else epilogue(std::false_type{}, std::false_type{});
+        }
+    }
+}
+
+// ---- host side --------------------------------------------------------------
+static int device_cus() {
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                    hipSuccess || n < 1)
+            n = 256;
+        cus = n;
+    }
+    return cus;
+}
+
+bool gemm_sk_applies(const DistArgs &a, int epi) {
+    if (epi != kEpiFilter || (a.prec != kPrecBF16 && a.prec != kPrecFP8)) return false;
+    if (const char *e = std::getenv("KNN_GEMM_SK"))
+        if (e[0] == '0') return false;
+    // (FP8 rows of more than 128 bytes need more registers than two waves per
+    // SIMD leave; they stay on the tiled product)
+    const bool kb_ok = a.prec == kPrecBF16 ? (a.ldq == 256 || a.ldq == 512) : a.ldq == 128;
+    // enough corpus tiles x row blocks to fill the device
+    return kb_ok && a.m >= 256 && a.n >= 8 * kSkCols;
+}
+
+template <int PREC, int KB>
+static hipError_t launch_sk_t(const DistArgs &a, hipStream_t stream) {
+    const uint32_t col_tiles = (uint32_t)((a.n + kSkCols - 1) / kSkCols);
+    const int64_t nrb = (a.m + 63) / 64;
+    // Row splits: the workgroups resident at a time are those of one split
+    // (consecutive ids), all streaming the same rows, so a split's query rows
+    // (about 2 MiB of operands) stay in the L2 of every XCD while its workgroups
+    // pass over them; and at least two workgroups per CU in all.
+    const int64_t rows_l2 = ((int64_t)(2u << 20) / a.ldq) / 64 * 64;
+    int64_t splits = (a.m + rows_l2 - 1) / (rows_l2 > 64 ? rows_l2 : 64);
+    const int64_t fill = (2 * (int64_t)device_cus() + col_tiles - 1) / col_tiles;
+    if (splits < fill) splits = fill;
+    const int64_t max_splits = nrb / 8 > 1 ? nrb / 8 : 1;  // >= 8 row blocks (two per row group of waves)
+    if (splits > max_splits) splits = max_splits;
+    if (splits < 1) splits = 1;
+    const uint64_t grid = (uint64_t)col_tiles * (uint64_t)splits;
+    if (grid > 0x7fffffffull) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((dist_gemm_sk_kernel<PREC, KB>), dim3((unsigned)grid), dim3(kSkThreads), 0, stream, a, col_tiles,
+                       (uint32_t)splits);
+    return hipGetLastError();
+}
+
+hipError_t launch_dist_gemm_sk(const DistArgs &a, hipStream_t stream) {
+    if (a.m == 0 || a.n == 0) return hipSuccess;
+    if (a.prec == kPrecBF16) {
+        if (a.ldq == 256) return launch_sk_t<kPrecBF16, 256>(a, stream);
+        if (a.ldq == 512) return launch_sk_t<kPrecBF16, 512>(a, stream);
+    } else if (a.prec == kPrecFP8) {
+        if (a.ldq == 128) return launch_sk_t<kPrecFP8, 128>(a, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace knn
