@@ -53,21 +53,27 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def measured_traffic():
-    """HBM bytes per launch of the fused product from the committed memory
-    counter summary, if the kernel source is unchanged since it was taken."""
+def measured_traffic(profile="knng_fused_262144x1024_k32_traffic.md", sources=("gemm.hip",), key=None):
+    """HBM bytes per launch from a committed memory-counter summary, if the
+    kernel sources it names are unchanged since the counters were taken.
+    `key` picks a `traffic_bytes_per_launch[key]` line instead of the plain one."""
     import hashlib
     import re
-    prof = os.path.join(ROOT, "profiles", "knng_fused_262144x1024_k32_traffic.md")
-    src = os.path.join(ROOT, "paper_1309_5478_amd", "csrc", "gemm.hip")
+    prof = os.path.join(ROOT, "profiles", profile)
     try:
         text = open(prof).read()
-        want = re.search(r"source_sha256: ([0-9a-f]{64})", text).group(1)
-        value = int(re.search(r"traffic_bytes_per_launch: (\d+)", text).group(1))
-        have = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        tag = re.escape(f"[{key}]") if key else ""
+        value = int(re.search(r"traffic_bytes_per_launch" + tag + r": (\d+)", text).group(1))
+        for name in sources:
+            src = os.path.join(ROOT, "paper_1309_5478_amd", "csrc", name)
+            want = re.search(r"source_sha256\(" + re.escape(name) + r"\): ([0-9a-f]{64})", text)
+            if want is None and name == sources[0]:
+                want = re.search(r"source_sha256: ([0-9a-f]{64})", text)
+            if want is None or hashlib.sha256(open(src, "rb").read()).hexdigest() != want.group(1):
+                return None
     except (OSError, AttributeError):
         return None
-    return value if have == want else None
+    return value
 
 
 def parity_block(Q, C, rows, gd, gi, od, oi, k, self_ids=None, band=1e-5, tol=1e-5):
@@ -346,11 +352,18 @@ def bench_select(args, knn, torch, np):
         res[f"k={k},{pivot}"] = {"ms": round(ms, 4), "GB/s": round(nbytes / ms / 1e6, 1),
                                  "passes_per_row": round(st["passes_total"] / M, 3),
                                  "streams_per_row": round(st["stream_passes_total"] / M, 4)}
+        if pivot == "sample":
+            res[f"k={k},{pivot}"]["traffic"] = measured_traffic("select_16384x65536_traffic.md", ("select.hip",),
+                                                                key=f"k={k}")
         log(f"select_k k={k} pivot={pivot}: {ms:.3f} ms, {nbytes / ms / 1e6:.0f} GB/s")
         if pivot == "sample" or args.select_case:
             tot_bytes += nbytes
             tot_ms += ms
     gbs = tot_bytes / tot_ms / 1e6
+    # HBM bytes per launch of the selection kernel, the mean over the timed k
+    # (from the committed counter summary; null if the kernel changed since)
+    tr = [v.get("traffic") for key, v in res.items() if key.endswith(",sample")]
+    traffic = round(sum(tr) / len(tr)) if tr and None not in tr else None
     cpu = None
     if args.cpu_rows > 0:
         import oracle
@@ -400,7 +413,7 @@ def bench_select(args, knn, torch, np):
                    "rows": M, "cols": N},
         "per_k": res,
         "roofline": {"bound": "hbm", "kernel": "select_rows_kernel", "achieved": round(gbs, 1),
-                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None},
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": traffic},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
@@ -582,7 +595,8 @@ def bench_lowprec(args, knn, torch, np, synth):
             h.graph(dev, k, precision=prec, flags=knn.FLAG_TIMING)
             h.stats()
         torch.cuda.synchronize()
-        tot = {"product_ms": 0.0, "product_flops": 0.0, "product_launches": 0, "fallback_rows": 0}
+        tot = {"product_ms": 0.0, "product_flops": 0.0, "product_launches": 0, "fallback_rows": 0,
+               "candidates_total": 0}
         t = time.perf_counter()
         for _ in range(steps):
             gd, gi = h.graph(dev, k, precision=prec, flags=knn.FLAG_TIMING)
@@ -598,7 +612,9 @@ def bench_lowprec(args, knn, torch, np, synth):
         r = {"ms_per_step": round(sec * 1e3, 2), "rows_per_s": round(N / sec, 1),
              "product_ms_per_launch": round(tot["product_ms"] / max(tot["product_launches"], 1), 3),
              "product_tflops": round(tf, 1), "frac_of_peak": round(tf / PEAK_MFMA_TFLOPS[prec], 4),
-             "fallback_rows_per_step": tot["fallback_rows"] / steps, "recall": recall, "max_rel_dist_err": rel}
+             "fallback_rows_per_step": tot["fallback_rows"] / steps,
+             "candidates_per_row": round(tot["candidates_total"] / steps / N, 1),
+             "recall": recall, "max_rel_dist_err": rel}
         log(f"knn_graph {prec}: {r['ms_per_step']} ms/step, {r['rows_per_s']:.0f} rows/s; product {tf:.1f} TFLOP/s"
             f" ({100 * r['frac_of_peak']:.1f} % of peak), recall {recall}, max rel. distance error {rel:.2e}")
         return r, tot
@@ -625,9 +641,11 @@ def bench_lowprec(args, knn, torch, np, synth):
                    "N": N, "d": d, "k": k, "oversample": 4},
         precs[0]: res,
         **others,
-        "roofline": {"bound": "mfma", "kernel": "dist_gemm_kernel (fused filter epilogue, BF16)",
+        "roofline": {"bound": "mfma", "kernel": "dist_gemm_sk_kernel (resident corpus, fused filter epilogue, BF16)",
                      "achieved": achieved, "peak": PEAK_MFMA_TFLOPS["bf16"], "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_MFMA_TFLOPS["bf16"], 4), "traffic": None,
+                     "frac": round(achieved / PEAK_MFMA_TFLOPS["bf16"], 4),
+                     "traffic": measured_traffic("lowprec_2p20x256_k64_traffic.md", ("gemm_sk.hip",))
+                     if precs[0] == "bf16" else None,
                      "launch_ms": res["product_ms_per_launch"],
                      "flops_per_launch": tot["product_flops"] / max(tot["product_launches"], 1)},
         "cpu_baseline": {"value": round(len(rows) / cpu_sec, 3), "unit": "rows/s", "cores": threads, "kind": "oracle",
