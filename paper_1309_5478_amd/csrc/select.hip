@@ -17,9 +17,10 @@
 //     one LDS atomic on the running counter (the paper's g< counter), and the
 //     survivors are written on chip (both buffers while streaming).  Keys at
 //     or above the pivot are not needed while L >= K (the paper's K < L case:
-//     only the left side is processed) and are not stored.  If L < K the left
-//     side is kept (pushed as a segment reference) and the row is streamed
-//     again for the band between the old pivot and a higher one.
+//     only the left side is processed) and are not stored.  If L < K every key
+//     of the left side belongs to the answer; the row is then streamed again
+//     from the start with a higher pivot, which keeps those keys and the band
+//     above them as one segment.
 //  3. Quickselect passes over the survivors, each a two-sided partition from one
 //     buffer into the other at the same positions (keys below the pivot from the
 //     left end, the others from the right end), K-versus-L recursion, and a stack
@@ -113,13 +114,13 @@ __device__ __forceinline__ void wave_append(SelSmem<CAP> &sm, const GBuf &gb, ui
     if (mine) vst_first(sm, gb, base + lanes_below(m), make_key(v, j));
 }
 
-// Generic vote of one entry per lane: key in [LO, P) (BAND) or below P, then
-// the wave append of the survivors.  Used for masked tails, band passes and
-// pivots in the NaN class or at the +infinity sentinel.
-template <int CAP, bool BAND>
+// Generic vote of one entry per lane: key below P, then the wave append of the
+// survivors.  Used for masked tails and pivots in the NaN class or at the
+// +infinity sentinel.
+template <int CAP>
 __device__ __forceinline__ void vote_generic(SelSmem<CAP> &sm, const GBuf &gb, float v, uint32_t j, bool valid,
-                                             const Pivot &P, const Pivot &LO) {
-    bool s = valid & key_below(v, j, P) & !(BAND && key_below(v, j, LO));
+                                             const Pivot &P) {
+    bool s = valid & key_below(v, j, P);
     uint64_t m = __ballot(s);
     if (m) wave_append(sm, gb, m, s, v, j);
 }
@@ -207,17 +208,17 @@ __device__ __forceinline__ void stream_tiles_le(SelSmem<CAP> &sm, const GBuf &gb
     }
 }
 
-// One streaming pass over the row, appending to buffer 0 the keys in [LO, P)
-// (BAND) or below P.  A threshold-form pivot (index ~0u) of a finite value
-// class on 16-byte aligned rows takes the tiled fast path for all full tiles;
-// everything else (band passes, NaN-class pivots, the +infinity sentinel,
-// misaligned rows, the ragged tail) takes the generic one-entry-per-lane loop.
-template <int CAP, bool BAND>
+// One streaming pass over the row, appending to buffer 0 the keys below P.  A
+// threshold-form pivot (index ~0u) of a finite value class on 16-byte aligned
+// rows takes the tiled fast path for all full tiles; everything else (NaN-class
+// pivots, the +infinity sentinel, misaligned rows, the ragged tail) takes the
+// generic one-entry-per-lane loop.
+template <int CAP>
 __device__ __forceinline__ void stream_pass(SelSmem<CAP> &sm, const GBuf &gb, const float *__restrict__ row,
-                                            uint32_t N, bool vec, const Pivot &P, const Pivot &LO) {
+                                            uint32_t N, bool vec, const Pivot &P) {
     const uint32_t tid = threadIdx.x;
     uint32_t done = 0;
-    if (!BAND && vec && !P.nan && !P.inf && P.pidx == 0xFFFFFFFFu) {
+    if (vec && !P.nan && !P.inf && P.pidx == 0xFFFFFFFFu) {
         const uint32_t full = (N >> 2) / kTile4;
         if (full > 0) stream_tiles_le(sm, gb, reinterpret_cast<const f32x4 *>(row), full, P.pv);
         done = full * kTile4 * 4;
@@ -226,7 +227,7 @@ __device__ __forceinline__ void stream_pass(SelSmem<CAP> &sm, const GBuf &gb, co
         uint32_t j = j0 + tid;
         bool valid = j < N;
         float v = valid ? row[j] : 0.f;
-        vote_generic<CAP, BAND>(sm, gb, v, j, valid, P, LO);
+        vote_generic<CAP>(sm, gb, v, j, valid, P);
     }
 }
 
@@ -533,7 +534,14 @@ __global__ __launch_bounds__(kSelThreads, KEYS ? 1 : (CAP == kSelectCap ? 5 : (C
                 if (!from_net) {
                     load_sample_blocks(sm, row, N);
                     sample_loaded = true;
-                    uint32_t rr0 = target_rank(kSortN, k, N, 3.0f, 3.0f);
+                    // aimed above the k-th key's expected sample rank: by three
+                    // standard deviations for k <= 64 (a short kept run), by two
+                    // for larger k, where fewer survivors mean fewer that
+                    // overflow the LDS buffers and a shorter final sort
+                    // (16384 x 65536, k = 1024: 0.44 -> 0.12 partition passes
+                    // per row)
+                    uint32_t rr0 = k <= (uint32_t)kWave ? target_rank(kSortN, k, N, 3.0f, 3.0f)
+                                                        : target_rank(kSortN, k, N, 2.0f, 1.0f);
                     if (rr0 < 8) {  // a few merge steps
                         if (wave == 0) {
                             uint64_t piv = merge_rank(sm, rr0);
@@ -560,41 +568,32 @@ __global__ __launch_bounds__(kSelThreads, KEYS ? 1 : (CAP == kSelectCap ? 5 : (C
             cyc_sample += t1 - t0;
             // threshold form: every key of the pivot's value class is below it
             P |= 0xFFFFFFFFull;
-            // 2. streaming passes until at least Kp keys are below the pivot
-            uint64_t LOk = 0;
-            uint32_t base = 0;
+            // 2. streaming passes until at least k keys are below the pivot.  A
+            // pass that keeps fewer is discarded and the row streamed again
+            // from the start with a higher pivot: the keys below the old pivot
+            // are below the new one too, so the buffer ends up holding what the
+            // kept run plus a band above it would hold, but as one active
+            // segment (no kept segment to carry, the direct finish stays open)
+            // and through the tiled pass.
             Kp = k;
             for (;;) {
-                if (tid == 0) sm.cnt_lt = base;
+                if (tid == 0) sm.cnt_lt = 0;
                 __syncthreads();
-                Pivot Pv = make_pivot(P);
-                if (LOk == 0) {
-                    stream_pass<CAP, false>(sm, gb, row, N, vec, Pv, Pv);
-                } else {
-                    Pivot Lv = make_pivot(LOk);
-                    stream_pass<CAP, true>(sm, gb, row, N, vec, Pv, Lv);
-                }
+                const Pivot Pv = make_pivot(P);
+                stream_pass<CAP>(sm, gb, row, N, vec, Pv);
                 __syncthreads();
-                uint32_t total = sm.cnt_lt;
+                const uint32_t total = sm.cnt_lt;
                 __syncthreads();
-                uint32_t L = total - base;
                 ++stream_passes;
-                if (stream_passes == 1) first = L;
+                if (stream_passes == 1) first = total;
                 if (total > 2u * CAP) spill = 1;
-                wide_lo = base;
+                wide_lo = 0;
                 wide_hi = total;
-                if (L >= Kp) {
-                    sb = 0; ss = base; se = total;
+                if (total >= k || P == kKeyMax) {  // (every key is below the sentinel)
+                    sb = 0; ss = 0; se = total;
                     break;
                 }
-                // too few below the pivot: keep them all, move the band up
-                if (wide_hi > (uint32_t)CAP) normalize_first(sm, gb, wide_lo, wide_hi);
-                wide_hi = 0;
-                push_seg(sm, gb, 0, base, total, nstack, agg, false);
-                Kp -= L;
-                base = total;
-                LOk = P;
-                if (P == kKeyMax) break;  // unreachable: every key is below the sentinel
+                const uint64_t LOk = P;
                 if (!sample_loaded) {
                     load_sample_blocks(sm, row, N);
                     sample_loaded = true;

@@ -35,7 +35,7 @@ def bits(a):
     return np.ascontiguousarray(a, dtype=np.float32).view(np.uint32)
 
 
-def check_select(h, torch, D, k, pivot, rows=None, ld_pad=0, offset=0, tag=""):
+def check_select(h, torch, D, k, pivot, rows=None, ld_pad=0, offset=0, tag="", flags=0):
     """Runs knn_select_k on D (optionally with padded rows / a misaligned base)
     and compares with the oracle on every (or the listed) row."""
     say(f"select_k {tag} shape={D.shape} k={k} pivot={pivot} ld_pad={ld_pad} offset={offset}")
@@ -45,7 +45,7 @@ def check_select(h, torch, D, k, pivot, rows=None, ld_pad=0, offset=0, tag=""):
     view[:, :C] = D
     dev = torch.from_numpy(host).cuda()
     dmat = dev[offset:offset + R * (C + ld_pad)].view(R, C + ld_pad)[:, :C]
-    vals, idx = h.select_k(dmat, k, pivot=pivot)
+    vals, idx = h.select_k(dmat, k, pivot=pivot, flags=flags)
     torch.cuda.synchronize()
     gv, gi = vals.cpu().numpy(), idx.cpu().numpy()
     ov, oi = oracle.select_k(D, k, rows=rows)
@@ -89,6 +89,32 @@ def test_select_adversarial_rows(h, torch, cols, pivot):
     D = np.stack([adv[n] for n in names])
     for k in (1, 32, 333, 1024):
         check_select(h, torch, D, k, pivot, tag="adversarial:" + ",".join(names))
+
+
+@pytest.mark.parametrize("cols", [65536, 70003])
+def test_select_band_restreams(h, torch, cols):
+    """Rows whose strided pivot sample (16 blocks of 64 entries at evenly spaced
+    starts) holds their smallest values: the first pivot keeps fewer than k keys,
+    so the row is streamed again for the next band of values, several times
+    (Methods: when fewer than k keys lie below the pivot they are all kept and
+    the search goes on above them).  Aligned rows take the tiled stream, the
+    misaligned base the generic one.  Rows whole (not split), so that each one's
+    sample is the one built here."""
+    import paper_1309_5478_amd as knn
+    rng = np.random.default_rng(21)
+    D = rng.uniform(1.0, 2.0, size=(8, cols)).astype(np.float32)
+    starts = [(b * (cols - 64)) // 15 for b in range(16)]
+    for r in range(8):
+        for s0 in starts:
+            D[r, s0:s0 + 64] = rng.uniform(0.0, 1e-3, 64)
+    D[1] = np.round(D[1] * 4) / 4          # ties at every band edge
+    D[2, starts[3]:starts[3] + 64] = -0.0
+    D[3, starts[5]:starts[5] + 64] = 0.0
+    for k in (32, 256, 1024):
+        st = check_select(h, torch, D, k, "sample", tag="band", flags=knn.FLAG_NO_SPLIT)
+        assert st["stream_passes_total"] > D.shape[0], "no row was streamed twice"
+        check_select(h, torch, D, k, "sample", offset=1, tag="band misaligned", flags=knn.FLAG_NO_SPLIT)
+        check_select(h, torch, D, k, "sample", tag="band, split rows")
 
 
 @pytest.mark.parametrize("pivot", PIVOTS)
