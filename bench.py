@@ -360,6 +360,22 @@ def bench_select(args, knn, torch, np):
             tot_bytes += nbytes
             tot_ms += ms
     gbs = tot_bytes / tot_ms / 1e6
+    # reference: a plain device-to-device copy (torch) of 2 GiB, bytes read +
+    # written per second, beside the 8 TB/s spec (never substituted for it)
+    del dev
+    src = torch.ones(1 << 29, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    c1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * src.numel() * 4 * 5 / c0.elapsed_time(c1) / 1e6
+    del src, dst
+    log(f"reference device copy: {copy_gbs:.0f} GB/s (read + write)")
     # HBM bytes per launch of the selection kernel, the mean over the timed k
     # (from the committed counter summary; null if the kernel changed since)
     tr = [v.get("traffic") for key, v in res.items() if key.endswith(",sample")]
@@ -412,6 +428,7 @@ def bench_select(args, knn, torch, np):
                                " k = 32, 256, 1024, sample pivots (one step = the three k)",
                    "rows": M, "cols": N},
         "per_k": res,
+        "reference_copy_GBps": round(copy_gbs, 1),
         "roofline": {"bound": "hbm", "kernel": "select_rows_kernel", "achieved": round(gbs, 1),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": traffic},
         "cpu_baseline": cpu,

@@ -38,8 +38,11 @@ struct Tile {
     static constexpr int BN = 32 * BJ * WN;
 };
 
+// 16-byte aligned: the staging writes and fragment reads are then single
+// ds_write_b128 / ds_read_b128 (8-byte alignment split each into two 8-byte
+// accesses; 16384-row BF16 product at d = 1024: 27.4 -> 24.4 ms)
 template <int BM, int BN, int ST>
-struct GemmSmem {
+struct __align__(16) GemmSmem {
     float A[ST][BM][kLdsStride];  // ST operand stages (2: double-buffered)
     float B[ST][BN][kLdsStride];
     float tau[BM];
