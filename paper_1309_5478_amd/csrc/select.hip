@@ -534,14 +534,16 @@ __global__ __launch_bounds__(kSelThreads, KEYS ? 1 : (CAP == kSelectCap ? 5 : (C
                 if (!from_net) {
                     load_sample_blocks(sm, row, N);
                     sample_loaded = true;
-                    // aimed above the k-th key's expected sample rank: by three
-                    // standard deviations for k <= 64 (a short kept run), by two
-                    // for larger k, where fewer survivors mean fewer that
+                    // aimed above the k-th key's expected sample rank mu: by
+                    // two standard deviations where the sample holds a few keys
+                    // below it (mu >= 4), where fewer survivors mean fewer that
                     // overflow the LDS buffers and a shorter final sort
                     // (16384 x 65536, k = 1024: 0.44 -> 0.12 partition passes
-                    // per row)
-                    uint32_t rr0 = k <= (uint32_t)kWave ? target_rank(kSortN, k, N, 3.0f, 3.0f)
-                                                        : target_rank(kSortN, k, N, 2.0f, 1.0f);
+                    // per row); by three and three more keys where it holds
+                    // hardly any, so that a row is rarely streamed twice (rows
+                    // of 2^20 at k = 1024: mu = 1)
+                    const bool few = (uint64_t)kSortN * k < 4ull * N;
+                    uint32_t rr0 = few ? target_rank(kSortN, k, N, 3.0f, 3.0f) : target_rank(kSortN, k, N, 2.0f, 1.0f);
                     if (rr0 < 8) {  // a few merge steps
                         if (wave == 0) {
                             uint64_t piv = merge_rank(sm, rr0);
@@ -932,7 +934,15 @@ hipError_t launch_select_keys(const SelectArgs &args, void *counter, int64_t row
 // A part is worth its own workgroup once it is long against the work that does
 // not scale with its length (the pivot sample, the final sort of about k keys
 // and the merge of its k keys): at least 4096 columns and 32 k.
-static uint64_t split_min_chunk(uint32_t k) { return k * 32ull > 4096ull ? k * 32ull : 4096ull; }
+// Smallest part: 32 k columns (a part's k keys stay a small fraction of it) and
+// at least 64 Ki columns when the split is chosen here: every part pays a fixed
+// cost (sample, sort, its list in the merge) that 16 KiB parts do not amortise
+// (8 rows of 2^20, k = 32: 181 us with 4 Ki-column parts, 56 us with 64 Ki).
+// A forced split goes down to 4 Ki columns.
+static uint64_t split_min_chunk(uint32_t k, bool force) {
+    const uint64_t floor = force ? 4096ull : 65536ull;
+    return k * 32ull > floor ? k * 32ull : floor;
+}
 
 SplitPlan select_split_plan(int64_t rows, uint32_t cols, uint32_t k, int num_cu, bool force) {
     SplitPlan sp{1, 1, cols, 0};
@@ -941,10 +951,11 @@ SplitPlan select_split_plan(int64_t rows, uint32_t cols, uint32_t k, int num_cu,
     if (rows < 1 || (!force && rows * 2 > resident)) return sp;
     uint32_t group = 2;
     while (2ull * group * k <= (uint64_t)kSelectKeysCap) group *= 2;
-    const uint64_t min_chunk = split_min_chunk(k);
-    // two workgroups' worth of parts per resident slot, so that dynamic row
-    // claiming evens out the parts' costs
-    const int64_t want = force ? INT64_MAX : 2 * resident;
+    const uint64_t min_chunk = split_min_chunk(k, force);
+    // parts for half the resident workgroups: fewer, longer parts measured
+    // faster than filling every slot (their streams are latency-bound, and each
+    // part's fixed cost grows the merge)
+    const int64_t want = force ? INT64_MAX : resident / 2;
     uint32_t parts = 1;
     while (parts < 4096u && rows * (int64_t)parts < want && (uint64_t)cols >= 2ull * parts * min_chunk) parts *= 2;
     for (; parts > 1; parts /= 2) {

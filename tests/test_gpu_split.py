@@ -68,13 +68,18 @@ def test_split_matches_oracle(h, torch, knn, rows, cols, pivot):
     for k in (1, 32, 100, 256, 1000, 1024):
         say(f"split rows={rows} cols={cols} k={k} pivot={pivot}")
         gv, gi, st = run(h, torch, knn, D, k, pivot=pivot, dev=dev)
-        if cols >= 2 * max(4096, 32 * k):
+        if cols >= 2 * max(65536, 32 * k):
             assert st["split_parts"] > 1, st
         assert st["rows"] == rows
         assert_oracle(D, k, gv, gi)
         nv, ni, nst = run(h, torch, knn, D, k, flags=knn.FLAG_NO_SPLIT, pivot=pivot, dev=dev)
         assert nst["split_parts"] == 1
         assert np.array_equal(bits(nv), bits(gv)) and np.array_equal(ni, gi)
+        # forced: parts down to max(4096, 32 k) columns
+        fv, fi, fst = run(h, torch, knn, D, k, flags=knn.FLAG_FORCE_SPLIT, pivot=pivot, dev=dev)
+        if cols >= 2 * max(4096, 32 * k):
+            assert fst["split_parts"] > 1, fst
+        assert np.array_equal(bits(fv), bits(gv)) and np.array_equal(fi, gi)
 
 
 def test_split_special_values_keep_their_bits(h, torch, knn):
