@@ -933,8 +933,7 @@ hipError_t launch_select_keys(const SelectArgs &args, void *counter, int64_t row
 // ---- rows split across workgroups -------------------------------------------
 // A part is worth its own workgroup once it is long against the work that does
 // not scale with its length (the pivot sample, the final sort of about k keys
-// and the merge of its k keys): at least 4096 columns and 32 k.
-// Smallest part: 32 k columns (a part's k keys stay a small fraction of it) and
+// and the merge of its k keys).  Smallest part: 32 k columns (a part's k keys stay a small fraction of it) and
 // at least 64 Ki columns when the split is chosen here: every part pays a fixed
 // cost (sample, sort, its list in the merge) that 16 KiB parts do not amortise
 // (8 rows of 2^20, k = 32: 181 us with 4 Ki-column parts, 56 us with 64 Ki).
