@@ -404,18 +404,17 @@ static hipError_t launch_gemm_t(const DistArgs &a0, hipStream_t stream) {
 // Tile shapes: small 128 x 128 (4 waves of 64 x 64), wide 128 x 256 (8 waves of
 // 64 x 64), big 256 x 256 (8 waves of 128 x 64; FP32 and BF16 only, its FP8
 // variant exceeds the register file), and small with one operand stage (half
-// the LDS: more workgroups per CU to hide load latency when the K loop is
-// short).  Default for products that fill the device: BF16 / FP8 with
-// d <= 512 small with one stage, otherwise big (wide for FP8); small for the
-// rest.  KNN_GEMM_TILE (small / wide / big / small1) overrides the default
-// where the shape is legal.
+// the LDS: more workgroups per CU to hide load latency).  Default: small with
+// one stage.  One chunk of prefetch inside a workgroup does not hide the loads
+// behind a chunk's MFMAs; more resident workgroups per CU do, in every
+// precision (32768 x 262144, d = 1024: BF16 22.6 ms against 24.4 for big and
+// 29.8 for wide; FP32 136.0 against 138.0 for big; 32768 x 2^20, d = 256,
+// FP32: 147.7 against 156.1).  KNN_GEMM_TILE (small / wide / big / small1)
+// overrides the default where the shape is legal.
 int gemm_tile_choice(const DistArgs &a) {
     if (a.tile >= kTileSmall && a.tile <= kTileSmall1)
         return (a.tile == kTileBig && a.prec == kPrecFP8) ? kTileWide : a.tile;
-    const bool large = a.m >= 2048 && a.n >= 2048;
-    int t = kTileSmall;
-    if (large && a.prec != kPrecF32 && a.d <= 512) t = kTileSmall1;  // short K loop: latency-bound
-    else if (large) t = a.prec == kPrecFP8 ? kTileWide : kTileBig;
+    int t = kTileSmall1;
     if (const char *e = std::getenv("KNN_GEMM_TILE")) {
         if (!std::strcmp(e, "small")) t = kTileSmall;
         else if (!std::strcmp(e, "wide")) t = kTileWide;
