@@ -882,12 +882,14 @@ knn_status_t run_batch(knn_handle_t h, const knn_job_t *jobs, int32_t njobs, hip
         KTRY(hipStreamSynchronize(stream));  // the host vectors above are released at scope end
         KTRY(launch_fill_u32(reinterpret_cast<uint32_t *>(b.sh.ninf), 1, 0xFF800000u, stream));
         const int prec = b.jobs[0].p.prec;
-        b.tile = prec == kPrecFP8 ? kTileWide : kTileBig;
+        b.tile = kTileSmall1;
         b.queue = false;
         // overrides of the default form (tests, measurements): KNN_GEMM_TILE
-        // small / wide / big, KNN_BATCH_QUEUE 1 / 0
+        // small / wide / big / small1, KNN_BATCH_QUEUE 1 / 0 (the queue form has
+        // no single-stage tile: small1 runs as small there)
         if (const char *te = std::getenv("KNN_GEMM_TILE")) {
-            if (!std::strcmp(te, "small")) b.tile = kTileSmall;
+            if (!std::strcmp(te, "small1")) b.tile = kTileSmall1;
+            else if (!std::strcmp(te, "small")) b.tile = kTileSmall;
             else if (!std::strcmp(te, "wide")) b.tile = kTileWide;
             else if (!std::strcmp(te, "big") && prec != kPrecFP8) b.tile = kTileBig;
         }
@@ -935,6 +937,7 @@ knn_status_t run_batch(knn_handle_t h, const knn_job_t *jobs, int32_t njobs, hip
                 if (prec != kPrecFP8) cands.push_back(kTileBig);
                 const size_t nshape = cands.size();
                 for (size_t i = 0; i < nshape; ++i) cands.push_back(cands[i] + kQueueChoice);
+                cands.push_back(kTileSmall1);  // one-item-per-workgroup form only
                 auto run = [&](int c) -> hipError_t {
                     const int tile = c % kQueueChoice;
                     hipError_t re = upload(tile);

@@ -335,14 +335,14 @@ __global__ __launch_bounds__(64 * WM * WN) void dist_gemm_kernel(DistArgs a) {
 // on XCD b % 8).  One item per workgroup, as in the single product: a
 // persistent loop over items would keep the tile set-up live across items and
 // spill.
-template <int WM, int WN, int BI, int BJ, int EPI, int PREC, bool VEC>
+template <int WM, int WN, int BI, int BJ, int EPI, int PREC, bool VEC, int ST>
 __global__ __launch_bounds__(64 * WM * WN) void dist_gemm_grouped_kernel(const DistArgs *__restrict__ jobs,
                                                                          const GemmItem *__restrict__ items) {
     using T = Tile<WM, WN, BI, BJ>;
-    __shared__ GemmSmem<T::BM, T::BN, 2> sm;
+    __shared__ GemmSmem<T::BM, T::BN, ST> sm;
     const GemmItem w = uniform_load(items + blockIdx.x);
     const DistArgs a = uniform_load(jobs + w.job);
-    gemm_tile<WM, WN, BI, BJ, EPI, PREC, VEC, 2>(a, w.tm, w.tn, sm);
+    gemm_tile<WM, WN, BI, BJ, EPI, PREC, VEC, ST>(a, w.tm, w.tn, sm);
 }
 
 // Persistent grouped product: a resident grid whose workgroups take items from
@@ -494,21 +494,21 @@ static hipError_t launch_queue_t(const DistArgs *jobs, const GemmItem *items, in
     return hipGetLastError();
 }
 
-template <int WM, int WN, int BI, int BJ, int EPI>
+template <int WM, int WN, int BI, int BJ, int EPI, int ST = 2>
 static hipError_t launch_grouped_t(const DistArgs *jobs, const GemmItem *items, int64_t grid, int prec,
                                    hipStream_t stream) {
     const dim3 g((unsigned)grid), b(Tile<WM, WN, BI, BJ>::NT);
     if (prec == kPrecBF16)
-        hipLaunchKernelGGL((dist_gemm_grouped_kernel<WM, WN, BI, BJ, EPI, kPrecBF16, true>), g, b, 0, stream, jobs,
+        hipLaunchKernelGGL((dist_gemm_grouped_kernel<WM, WN, BI, BJ, EPI, kPrecBF16, true, ST>), g, b, 0, stream, jobs,
                            items);
     else if (prec == kPrecFP8) {
         if constexpr (BI * BJ <= 4)
-            hipLaunchKernelGGL((dist_gemm_grouped_kernel<WM, WN, BI, BJ, EPI, kPrecFP8, true>), g, b, 0, stream, jobs,
-                               items);
+            hipLaunchKernelGGL((dist_gemm_grouped_kernel<WM, WN, BI, BJ, EPI, kPrecFP8, true, ST>), g, b, 0, stream,
+                               jobs, items);
         else
             return hipErrorInvalidValue;
     } else
-        hipLaunchKernelGGL((dist_gemm_grouped_kernel<WM, WN, BI, BJ, EPI, kPrecF32, true>), g, b, 0, stream, jobs,
+        hipLaunchKernelGGL((dist_gemm_grouped_kernel<WM, WN, BI, BJ, EPI, kPrecF32, true, ST>), g, b, 0, stream, jobs,
                            items);
     return hipGetLastError();
 }
@@ -542,6 +542,7 @@ hipError_t launch_dist_gemm_grouped(const DistArgs *jobs, const GemmItem *items,
                 return launch_grouped_t<2, 4, 4, 2, kEpiFilter>(jobs, items, grid, kPrecBF16, stream);
             return launch_grouped_t<2, 4, 4, 2, kEpiFilter>(jobs, items, grid, kPrecF32, stream);
         case kTileWide: return launch_grouped_t<2, 4, 2, 2, kEpiFilter>(jobs, items, grid, prec, stream);
+        case kTileSmall1: return launch_grouped_t<2, 2, 2, 2, kEpiFilter, 1>(jobs, items, grid, prec, stream);
         default: return launch_grouped_t<2, 2, 2, 2, kEpiFilter>(jobs, items, grid, prec, stream);
     }
 }
