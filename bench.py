@@ -120,7 +120,8 @@ def main():
     ap.add_argument("--no-pivot-compare", action="store_true", help="skip the per-pivot-rule steps")
     ap.add_argument("--cpu-rows", type=int, default=1536, help="query rows in the CPU oracle sample (0: skip)")
     ap.add_argument("--no-bf16", action="store_true", help="skip the BF16-product row of the k-NNG workload")
-    ap.add_argument("--workload", default="knng", choices=["knng", "batch", "select", "lowprec", "sweep", "hostcorpus"])
+    ap.add_argument("--workload", default="knng",
+                    choices=["knng", "small", "batch", "select", "lowprec", "sweep", "hostcorpus"])
     ap.add_argument("--batch-jobs", type=int, default=512)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference dispatch for memory counters)")
@@ -159,6 +160,8 @@ def main():
         return bench_sweep(args, knn, torch, np, synth)
     if args.workload == "hostcorpus":
         return bench_hostcorpus(args, knn, torch, np, synth)
+    if args.workload == "small":
+        return bench_small(args, knn, torch, np, synth)
     N, d, k = args.n, args.d, args.k
     t0 = time.perf_counter()
     P = synth.gmm_points(N, d, seed=synth.SEEDS["knng_fused"])
@@ -322,6 +325,73 @@ def main():
         sys.exit(1)
 
 
+def bench_small(args, knn, torch, np, synth):
+    """The smallest graph configuration: N = 4096 uniform[0,1) points in d = 128,
+    k = 16, the own point excluded.  Launch- and latency-bound (4.3e9 flops), so
+    the roofline fraction only says how far from compute-bound it is.  One step
+    is one knn_graph call, timed fused (threshold filter in the product) and
+    unfused (the distance matrix materialised, then select_k: the paper's
+    two-step pipeline); every row of both is checked against the oracle, which
+    is timed on all rows on all host threads and on one."""
+    import oracle
+    N, d, k = 4096, 128, 16
+    P = synth.uniform_points(N, d, seed=synth.SEEDS["knng_small"])
+    dev = torch.from_numpy(P).cuda()
+    torch.cuda.synchronize()
+    h = knn.Handle(0)
+    rows = np.arange(N)
+    threads = oracle.default_threads()
+    a = time.perf_counter()
+    od, oi = oracle.knn(P, P, k + 1, self_ids=rows, nthreads=threads)
+    cpu_sec = time.perf_counter() - a
+    a = time.perf_counter()
+    oracle.knn(P, P, k + 1, self_ids=rows, nthreads=1)
+    cpu1_sec = time.perf_counter() - a
+    res = {}
+    for tag, flags in (("fused", 0), ("unfused", knn.FLAG_UNFUSED)):
+        for _ in range(max(args.warmup, 1)):
+            h.graph(dev, k, flags=flags)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            gd, gi = h.graph(dev, k, flags=flags)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        gd, gi = gd.cpu().numpy(), gi.cpu().numpy()
+        par = parity_block(P, P, rows, gd, gi, od, oi, k, self_ids=rows)
+        res[tag] = {"ms_per_call": round(ms, 4), "rows_per_s": round(N / ms * 1e3, 1), "parity": par}
+        log(f"knn_graph {tag} N={N} d={d} k={k}: {ms:.3f} ms per call; parity {par}")
+    flops = 2.0 * N * N * d
+    ms = res["fused"]["ms_per_call"]
+    line = {
+        "metric": "k-NNG rows/s (N=4096, d=128, k=16, uniform; launch-bound)",
+        "value": res["fused"]["rows_per_s"],
+        "unit": "rows/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "k-NNG, N=4096, d=128, k=16, uniform[0,1), own point excluded; fused and unfused",
+                   "N": N, "d": d, "k": k},
+        "per_path": res,
+        "roofline": {"bound": "mfma", "kernel": "whole knn_graph call (latency-bound: a few launches of a few us)",
+                     "achieved": round(flops / ms / 1e9, 2), "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(flops / ms / 1e9 / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": None},
+        "cpu_baseline": {"value": round(N / cpu_sec, 1), "unit": "rows/s", "cores": threads, "kind": "oracle",
+                         "sample": f"all {N} rows (FP64 direct distances + stable sort), {cpu_sec:.2f} s",
+                         "one_core": {"value": round(N / cpu1_sec, 1), "unit": "rows/s", "cores": 1,
+                                      "sample": f"all {N} rows on one thread, {cpu1_sec:.2f} s"}},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def bench_select(args, knn, torch, np):
     import synth
     M, N, d = 16384, 65536, 256
@@ -440,7 +510,9 @@ def bench_sweep(args, knn, torch, np, synth):
     """The paper's saturation workload shape (Results, Figure 8): rows of
     n = 2^20 uniform[0,1) values, Q = 8 ... 256 rows, k = 32 and 1024, with
     rows split across workgroups (default) and without (one workgroup per row,
-    as the paper's method); time per row and GB/s.  Beside it the CPU selection
+    as the paper's method); time per row and GB/s.  Then the shapes of its
+    comparisons (Figures 6 and 7): a fixed n Q = 2^27 values, Q = 2^3 ... 2^14,
+    k = 32 and 512, GB/s against log2(n / Q).  Beside it the CPU selection
     baseline (nth_element + sort of k) at Q = 256, one core and all cores."""
     n = 1 << 20
     Qmax = 256
@@ -469,6 +541,32 @@ def bench_sweep(args, knn, torch, np, synth):
                                               "GB/s": round(nbytes / ms / 1e6, 1), "parts": parts}
                 log(f"sweep k={k} Q={Q} {tag}: {ms:.3f} ms, {1e3 * ms / Q:.2f} us/row, {nbytes / ms / 1e6:.0f} GB/s,"
                     f" parts {parts}")
+    # fixed total size n Q = 2^27 (the paper's comparison shapes, Results,
+    # Figures 6-7): Q = 2^3 ... 2^14 rows, GB/s against log2(n / Q)
+    del dev
+    flat = torch.from_numpy(synth.uniform_points(1 << 13, 1 << 14, seed=synth.SEEDS["sweep"] + 100)).cuda().view(-1)
+    torch.cuda.synchronize()
+    fixed = {}
+    for k in (32, 512):
+        for lq in range(3, 15):
+            Q, n2 = 1 << lq, 1 << (27 - lq)
+            sub = flat.view(Q, n2)
+            for _ in range(max(args.warmup, 1)):
+                h.select_k(sub, k)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(args.steps):
+                h.select_k(sub, k)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+            nbytes = 4 * Q * n2 + 8 * Q * k
+            fixed[f"k={k},log2(n/Q)={27 - 2 * lq}"] = {"Q": Q, "n": n2, "ms": round(ms, 4),
+                                                       "GB/s": round(nbytes / ms / 1e6, 1),
+                                                       "parts": h.stats()["split_parts"]}
+            log(f"n Q = 2^27, k={k}, Q={Q}, n={n2}: {ms:.3f} ms, {nbytes / ms / 1e6:.0f} GB/s")
+    del flat
     cpu = None
     if args.cpu_rows > 0:
         import oracle
@@ -501,6 +599,7 @@ def bench_sweep(args, knn, torch, np, synth):
         "config": {"workload": "select_k on Q x 2^20 uniform[0,1) FP32 rows, Q = 8 ... 256, k = 32 and 1024;"
                                " value: Q = 8, k = 32, rows split across workgroups", "n": n},
         "per_case": res,
+        "fixed_total_2p27": fixed,
         "roofline": {"bound": "hbm", "kernel": "select_rows_kernel (parts) + key-list merges",
                      "achieved": head["GB/s"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(head["GB/s"] / PEAK_HBM_GBS, 4), "traffic": None},
@@ -600,7 +699,7 @@ def bench_lowprec(args, knn, torch, np, synth):
     dev = torch.from_numpy(P).cuda()
     torch.cuda.synchronize()
     h = knn.Handle(0)
-    rows = np.random.default_rng(0).choice(N, 32, replace=False)
+    rows = np.random.default_rng(0).choice(N, 256, replace=False)
     import oracle
     threads = oracle.default_threads()
     a = time.perf_counter()
@@ -613,7 +712,7 @@ def bench_lowprec(args, knn, torch, np, synth):
             h.stats()
         torch.cuda.synchronize()
         tot = {"product_ms": 0.0, "product_flops": 0.0, "product_launches": 0, "fallback_rows": 0,
-               "candidates_total": 0}
+               "candidates_total": 0, "rows_uncertified": 0}
         t = time.perf_counter()
         for _ in range(steps):
             gd, gi = h.graph(dev, k, precision=prec, flags=knn.FLAG_TIMING)
@@ -624,14 +723,17 @@ def bench_lowprec(args, knn, torch, np, synth):
         g = gi.cpu().numpy()[rows]
         gdist = gd.cpu().numpy()[rows].astype(np.float64)
         recall = sum(len(set(x.tolist()) & set(y.tolist())) for x, y in zip(g, oi)) / (len(rows) * k)
-        rel = float(np.max(np.abs(gdist - od) / np.maximum(np.abs(od), 1e-30)))
+        relv = np.abs(gdist - od) / np.maximum(np.abs(od), 1e-30)
+        rel = float(np.max(relv))
         tf = tot["product_flops"] / (tot["product_ms"] / 1e3) / 1e12 if tot["product_ms"] > 0 else 0.0
         r = {"ms_per_step": round(sec * 1e3, 2), "rows_per_s": round(N / sec, 1),
              "product_ms_per_launch": round(tot["product_ms"] / max(tot["product_launches"], 1), 3),
              "product_tflops": round(tf, 1), "frac_of_peak": round(tf / PEAK_MFMA_TFLOPS[prec], 4),
              "fallback_rows_per_step": tot["fallback_rows"] / steps,
              "candidates_per_row": round(tot["candidates_total"] / steps / N, 1),
-             "recall": recall, "max_rel_dist_err": rel}
+             "certified_fraction": round(1.0 - tot["rows_uncertified"] / (steps * N), 4),
+             "recall": recall, "max_rel_dist_err": rel, "mean_rel_dist_err": float(np.mean(relv)),
+             "oracle_rows": int(len(rows))}
         log(f"knn_graph {prec}: {r['ms_per_step']} ms/step, {r['rows_per_s']:.0f} rows/s; product {tf:.1f} TFLOP/s"
             f" ({100 * r['frac_of_peak']:.1f} % of peak), recall {recall}, max rel. distance error {rel:.2e}")
         return r, tot
