@@ -121,8 +121,8 @@ typedef struct {
 #define KNN_FLAG_FORCE_RERUN 0x20
 /* knn_select_k: never split rows across workgroups (see knn_select_k). */
 #define KNN_FLAG_NO_SPLIT 0x40
-/* knn_select_k: split every row that is at least two minimal parts long,
- * whatever the row count (tests). */
+/* knn_select_k: split every row that is at least two minimal parts of
+ * max(4096, 32 k) columns long, whatever the row count (tests). */
 #define KNN_FLAG_FORCE_SPLIT 0x80
 
 typedef struct {
@@ -171,10 +171,11 @@ const char *knn_last_error(knn_handle_t h);
  * Few long rows: the paper's GPU is only saturated with enough rows in flight
  * (Results, Figure 8; Discussion).  When the rows are too few to give every
  * resident workgroup one, each row is cut into parts of at least
- * max(4096, 32 k) columns (a power of two of them), every part's k smallest
- * keys are selected by its own workgroup, and the parts' lists are merged by
- * key-list selections; the result is the same, bit for bit.  The flags
- * KNN_FLAG_NO_SPLIT / KNN_FLAG_FORCE_SPLIT turn this off / force it.
+ * max(65536, 32 k) columns (a power of two of them; max(4096, 32 k) when
+ * forced), every part's k smallest keys are selected by its own workgroup, and
+ * the parts' lists are merged by key-list selections; the result is the same,
+ * bit for bit.  The flags KNN_FLAG_NO_SPLIT / KNN_FLAG_FORCE_SPLIT turn this
+ * off / force it.
  *
  *   dist     rows x cols FP32, row stride ld (>= cols)            [in, device]
  *   k        1 <= k <= min(cols, 1024)
