@@ -1,6 +1,6 @@
 // Short-K distance product for BF16 / FP8 operands with the threshold filter
 // (the fused first pass of the quick multi-select), for short operand rows
-// (BF16 d <= 256, FP8 d <= 128).
+// (BF16 d <= 256, FP8 d <= 256).
 //
 // With so short a K loop, the one-tile-per-workgroup product of gemm.hip spends
 // most of its time waiting: each tile's operands arrive one 128-byte chunk ahead
@@ -140,24 +140,36 @@ __global__ __launch_bounds__(kSkThreads) void dist_gemm_sk_kernel(DistArgs a, ui
         const int64_t nxt = rb + 4;
         const bool more = nxt < rb1;
         f32x16 acc[2][4];
-        // corpus fragments one k-step ahead: the next step's LDS reads are in
-        // flight during this step's MFMAs
+        // BF16: the k-steps unrolled, each step's corpus fragments read from LDS
+        // during the previous step's MFMAs.  FP8 (fragments twice the size):
+        // one k-step at a time, each fragment read where it is used, so that
+        // the 2 x 4 accumulator blocks and the rest fit in 256 registers
+        // (unrolled or read ahead, the FP8 loop spills)
+        constexpr bool AHEAD = PREC != kPrecFP8;
         F bcur[4], bnxt[4];
+        if constexpr (AHEAD) {
 #pragma unroll
-        for (int bj = 0; bj < 4; ++bj) bcur[bj] = bfrag(0, bj);
-#pragma unroll
+            for (int bj = 0; bj < 4; ++bj) bcur[bj] = bfrag(0, bj);
+        }
+#pragma unroll(PREC == kPrecFP8 ? 1 : S)
         for (int s = 0; s < S; ++s) {
-            if (s + 1 < S) {
+            if constexpr (AHEAD) {
+                if (s + 1 < S) {
 #pragma unroll
-                for (int bj = 0; bj < 4; ++bj) bnxt[bj] = bfrag(s + 1, bj);
+                    for (int bj = 0; bj < 4; ++bj) bnxt[bj] = bfrag(s + 1, bj);
+                }
             }
 #pragma unroll
-            for (int bj = 0; bj < 4; ++bj)
+            for (int bj = 0; bj < 4; ++bj) {
+                const F b = AHEAD ? bcur[bj] : bfrag(s, bj);
 #pragma unroll
                 for (int bi = 0; bi < 2; ++bi)
-                    acc[bi][bj] = mfma<PREC>(ring[s % P][bi], bcur[bj], s == 0 ? zero : acc[bi][bj]);
+                    acc[bi][bj] = mfma<PREC>(ring[s % P][bi], b, s == 0 ? zero : acc[bi][bj]);
+            }
+            if constexpr (AHEAD) {
 #pragma unroll
-            for (int bj = 0; bj < 4; ++bj) bcur[bj] = bnxt[bj];
+                for (int bj = 0; bj < 4; ++bj) bcur[bj] = bnxt[bj];
+            }
             // refill the slot just read: this block's step s + P, or the next block's
             if (s + P < S) {
                 ring[s % P][0] = qfrag(rb, s + P, 0);
@@ -272,9 +284,9 @@ bool gemm_sk_applies(const DistArgs &a, int epi) {
     if (epi != kEpiFilter || (a.prec != kPrecBF16 && a.prec != kPrecFP8)) return false;
     if (const char *e = std::getenv("KNN_GEMM_SK"))
         if (e[0] == '0') return false;
-    // (FP8 rows of more than 128 bytes need more registers than two waves per
-    // SIMD leave; they stay on the tiled product)
-    const bool kb_ok = a.prec == kPrecBF16 ? (a.ldq == 256 || a.ldq == 512) : a.ldq == 128;
+    // (FP8 rows of more than 256 bytes are left to the tiled product: not
+    // measured here)
+    const bool kb_ok = a.prec == kPrecBF16 ? (a.ldq == 256 || a.ldq == 512) : (a.ldq == 128 || a.ldq == 256);
     // enough corpus tiles x row blocks to fill the device
     return kb_ok && a.m >= 256 && a.n >= 8 * kSkCols;
 }
@@ -308,6 +320,7 @@ hipError_t launch_dist_gemm_sk(const DistArgs &a, hipStream_t stream) {
         if (a.ldq == 512) return launch_sk_t<kPrecBF16, 512>(a, stream);
     } else if (a.prec == kPrecFP8) {
         if (a.ldq == 128) return launch_sk_t<kPrecFP8, 128>(a, stream);
+        if (a.ldq == 256) return launch_sk_t<kPrecFP8, 256>(a, stream);
     }
     return hipErrorInvalidValue;
 }

@@ -202,11 +202,12 @@ def test_batch_timing_and_autotune(h, knn, torch, data):
 
 def test_batch_queue_form_same_bits(knn, torch, data):
     """The product as a resident grid over per-XCD item queues gives the same
-    bits as one workgroup per item, for every tile shape."""
+    bits as one workgroup per item, for every tile shape (small1: the
+    single-stage tile, one workgroup per item only)."""
     jobs = job_list(data)
     want = None
-    for tile in ("small", "wide", "big"):
-        for queue in ("0", "1"):
+    for tile in ("small", "small1", "wide", "big"):
+        for queue in (("0",) if tile == "small1" else ("0", "1")):
             os.environ["KNN_GEMM_TILE"] = tile
             os.environ["KNN_BATCH_QUEUE"] = queue
             try:

@@ -44,7 +44,8 @@ def run(h, torch, Q, C, k, prec, sk, graph=False):
     return d.cpu().numpy(), i.cpu().numpy()
 
 
-@pytest.mark.parametrize("prec,d", [("bf16", 256), ("bf16", 100), ("bf16", 128), ("fp8", 128), ("fp8", 77)])
+@pytest.mark.parametrize("prec,d", [("bf16", 256), ("bf16", 100), ("bf16", 128), ("fp8", 128), ("fp8", 77),
+                                    ("fp8", 256), ("fp8", 200)])
 @pytest.mark.parametrize("graph", [False, True])
 def test_sk_equals_tiled(h, torch, prec, d, graph):
     """Ragged sizes (rows not a multiple of 64, columns not of 256), mixture data,
