@@ -7,21 +7,24 @@
 // of the matrix cores, the first chunk and the epilogue are not overlapped, and
 // LDS carries both operands.  Here a workgroup of eight waves keeps one corpus
 // tile of 256 columns (the whole K) resident in LDS and walks its range of query
-// rows; each wave computes 64 rows x 128 columns per step and reads its query
-// fragments straight from global memory into registers, a few k-steps ahead, in
-// a ring that runs on from one row block into the next, so loads are in flight
-// during the MFMAs and during the epilogue.  The waves never wait for each
+// rows; each wave computes 32 rows x all 256 columns per step (each query
+// fragment feeds eight MFMAs, the corpus fragments come from LDS) and reads its
+// query fragments straight from global memory into registers, a few k-steps
+// ahead, in a ring that runs on from one row block into the next, so loads are
+// in flight during the MFMAs and during the epilogue.  The waves never wait for each
 // other after the corpus tile is loaded, so one wave's epilogue overlaps the
 // other waves' MFMAs on the same SIMD.
 //
 // Each dot product uses the same MFMA instruction over the same k-steps in the
 // same order as gemm.hip, so the reduced keys are the same bits.
 //
-// Measured at 2^20 x 256 BF16: 636 TFLOP/s per launch against 464 for the tiled
-// product; without the epilogue the loop reaches 920, and with the query
-// fragments read from LDS instead of global memory 1300: what bounds it is the
-// query fragment loads, each touching 32 rows for 32 bytes apiece (the MFMA
-// operand layout), and then the epilogue.
+// Measured at 2^20 x 256 BF16: 700 TFLOP/s per launch against 464 for the tiled
+// product.  With waves of 64 rows x 128 columns (a query fragment feeding four
+// MFMAs, both column halves loading the same fragments) it was 636; without the
+// epilogue that loop reached 920, and with the query fragments read from LDS
+// instead of global memory 1300: what bounds it is the query fragment loads,
+// each touching 32 rows for 32 bytes apiece (the MFMA operand layout), and then
+// the epilogue.
 #include <cstdlib>
 #include <cstring>
 #include <type_traits>
@@ -39,7 +42,7 @@ typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kSkCols = 256;   // corpus columns resident per workgroup
-constexpr int kSkWaves = 8;    // 4 row groups x 2 column halves
+constexpr int kSkWaves = 8;    // 8 row groups of 32 rows, each wave all 256 columns
 constexpr int kSkThreads = 64 * kSkWaves;
 constexpr int kSkPad = 16;     // bytes of padding per LDS row (conflict-free 16-byte reads)
 
@@ -75,22 +78,22 @@ __device__ __forceinline__ F load_frag(const unsigned char *p) {
 }  // namespace
 
 // grid: col_tiles x row_splits workgroups; workgroup b takes corpus tile
-// b % col_tiles and row split b / col_tiles (row blocks of 64).
+// b % col_tiles and row split b / col_tiles (row blocks of 32, one per wave in
+// turn).
 template <int PREC, int KB>
 __global__ __launch_bounds__(kSkThreads) void dist_gemm_sk_kernel(DistArgs a, uint32_t col_tiles, uint32_t row_splits) {
     using T = Sk<PREC, KB>;
     using F = typename T::frag;
     constexpr int S = T::STEPS, P = T::P, LS = T::LS, STEP = T::STEP;
+    constexpr int NB = 8;  // column blocks of 32 per wave
     __shared__ __align__(16) unsigned char sB[kSkCols * LS];
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
     const uint32_t h = lane / 32, l32 = lane % 32;
-    const uint32_t half = wave / 4, wr = wave % 4;
     const uint32_t ct = blockIdx.x % col_tiles, rs = blockIdx.x / col_tiles;
     const int64_t col0 = (int64_t)ct * kSkCols;
-    const int64_t nrb = (a.m + 63) / 64;
+    const int64_t nrb = (a.m + 31) / 32;
     const int64_t rb0 = nrb * rs / row_splits, rb1 = nrb * (rs + 1) / row_splits;
 
-    // 1. the corpus tile, whole K, into LDS (columns beyond n are zero)
     const unsigned char *Cq = static_cast<const unsigned char *>(a.Cq);
     constexpr int PER_ROW = KB / 16;
     for (int p = (int)tid; p < kSkCols * PER_ROW; p += kSkThreads) {
@@ -99,102 +102,71 @@ __global__ __launch_bounds__(kSkThreads) void dist_gemm_sk_kernel(DistArgs a, ui
         if (col0 + r < a.n) v = *reinterpret_cast<const i32x4 *>(Cq + (col0 + r) * a.ldq + c * 16);
         *reinterpret_cast<i32x4 *>(sB + r * LS + c * 16) = v;
     }
-    // this lane's four columns: norms, scales (-2 x column scale) and bounds
-    float cn[4], cs[4];
-    uint32_t gj[4];  // (column indices are below 2^31)
+    float cn[NB], cs[NB];
 #pragma unroll
-    for (int bj = 0; bj < 4; ++bj) {
-        const int64_t j = col0 + half * 128 + bj * 32 + l32;
-        gj[bj] = (uint32_t)j;
+    for (int bj = 0; bj < NB; ++bj) {
+        const int64_t j = col0 + bj * 32 + l32;
         const bool in = j < a.n;
-        cn[bj] = in ? a.cnorm[gj[bj]] : 0.f;
-        cs[bj] = (PREC == kPrecFP8 && in) ? -2.0f * a.cscale[gj[bj]] : -2.0f;
+        cn[bj] = in ? a.cnorm[j] : 0.f;
+        cs[bj] = (PREC == kPrecFP8 && in) ? -2.0f * a.cscale[j] : -2.0f;
     }
-    const int64_t cw0 = col0 + half * 128;  // first column of this wave
+    const uint32_t gj0 = (uint32_t)(col0 + l32);
     __syncthreads();
 
     const unsigned char *Qq = static_cast<const unsigned char *>(a.Qq);
     const int64_t mlast = a.m - 1;
-    // query fragment (row block rb, k-step s, 32-row block bi); rows beyond m
-    // read row m - 1 (their results are never kept)
-    auto qfrag = [&](int64_t rb, int s, int bi) -> F {
-        int64_t row = rb * 64 + bi * 32 + l32;
+    // query fragment (row block rb, k-step s); rows beyond m read row m - 1
+    // (their results are never kept)
+    auto qfrag = [&](int64_t rb, int s) -> F {
+        int64_t row = rb * 32 + l32;
         row = row < mlast ? row : mlast;
         return load_frag<F>(Qq + row * a.ldq + s * STEP + h * (STEP / 2));
     };
     auto bfrag = [&](int s, int bj) -> F {
-        return load_frag<F>(sB + (half * 128 + bj * 32 + l32) * LS + s * STEP + h * (STEP / 2));
+        return load_frag<F>(sB + (bj * 32 + l32) * LS + s * STEP + h * (STEP / 2));
     };
 
-    F ring[P][2];
-    int64_t rb = rb0 + wr;
+    F ring[P];
+    int64_t rb = rb0 + wave;
     if (rb < rb1) {
 #pragma unroll
-        for (int p = 0; p < P; ++p) {
-            ring[p][0] = qfrag(rb, p, 0);
-            ring[p][1] = qfrag(rb, p, 1);
-        }
+        for (int p = 0; p < P; ++p) ring[p] = qfrag(rb, p);
     }
     const f32x16 zero = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    for (; rb < rb1; rb += 4) {
-        const int64_t nxt = rb + 4;
+    for (; rb < rb1; rb += kSkWaves) {
+        const int64_t nxt = rb + kSkWaves;
         const bool more = nxt < rb1;
-        f32x16 acc[2][4];
-        // BF16: the k-steps unrolled, each step's corpus fragments read from LDS
-        // during the previous step's MFMAs.  FP8 (fragments twice the size):
-        // one k-step at a time, each fragment read where it is used, so that
-        // the 2 x 4 accumulator blocks and the rest fit in 256 registers
-        // (unrolled or read ahead, the FP8 loop spills)
-        constexpr bool AHEAD = PREC != kPrecFP8;
-        F bcur[4], bnxt[4];
-        if constexpr (AHEAD) {
-#pragma unroll
-            for (int bj = 0; bj < 4; ++bj) bcur[bj] = bfrag(0, bj);
-        }
+        f32x16 acc[NB];
+        // each corpus fragment is read from LDS where it is used; BF16 takes
+        // the k-steps unrolled, FP8 (fragments twice the size) one at a time,
+        // so that the eight accumulator blocks and the rest fit 256 registers
 #pragma unroll(PREC == kPrecFP8 ? 1 : S)
         for (int s = 0; s < S; ++s) {
-            if constexpr (AHEAD) {
-                if (s + 1 < S) {
 #pragma unroll
-                    for (int bj = 0; bj < 4; ++bj) bnxt[bj] = bfrag(s + 1, bj);
-                }
-            }
-#pragma unroll
-            for (int bj = 0; bj < 4; ++bj) {
-                const F b = AHEAD ? bcur[bj] : bfrag(s, bj);
-#pragma unroll
-                for (int bi = 0; bi < 2; ++bi)
-                    acc[bi][bj] = mfma<PREC>(ring[s % P][bi], b, s == 0 ? zero : acc[bi][bj]);
-            }
-            if constexpr (AHEAD) {
-#pragma unroll
-                for (int bj = 0; bj < 4; ++bj) bcur[bj] = bnxt[bj];
+            for (int bj = 0; bj < NB; ++bj) {
+                const F b = bfrag(s, bj);
+                acc[bj] = mfma<PREC>(ring[s % P], b, s == 0 ? zero : acc[bj]);
             }
             // refill the slot just read: this block's step s + P, or the next block's
-            if (s + P < S) {
-                ring[s % P][0] = qfrag(rb, s + P, 0);
-                ring[s % P][1] = qfrag(rb, s + P, 1);
-            } else if (more) {
-                ring[s % P][0] = qfrag(nxt, s + P - S, 0);
-                ring[s % P][1] = qfrag(nxt, s + P - S, 1);
-            }
+            if (s + P < S) ring[s % P] = qfrag(rb, s + P);
+            else if (more) ring[s % P] = qfrag(nxt, s + P - S);
             // keep the loads where the ring puts them (the scheduler would
             // otherwise hoist every step's loads and run out of registers)
             __builtin_amdgcn_sched_barrier(0);
         }
 
-        // epilogue: lane l holds row rb * 64 + l's threshold, scale and id;
-        // element (bi, bj, r) is row bi*32 + 8*(r/4) + 4h + r%4, column gj[bj]
-        const int64_t myrow = rb * 64 + lane;
+        // epilogue: lanes 0..31 hold rows rb * 32 + l32's threshold, scale and id;
+        // element (bj, r) is row 8*(r/4) + 4h + r%4, column gj0 + 32 bj
+        const int64_t myrow = rb * 32 + l32;
         const bool rin = myrow < a.m;
         const float tau_l = rin ? a.tau[myrow * a.tau_stride] : 0.f;
         const float qs_l = (PREC == kPrecFP8 && rin) ? a.qscale[myrow] : 1.f;
         int64_t qid_l = -1;
         if (a.self_offset >= 0 && rin) qid_l = a.self_offset + (a.row_ids ? (int64_t)a.row_ids[myrow] : myrow);
-        const bool may_self = __ballot(qid_l >= cw0 && qid_l < cw0 + 128) != 0;
-        // the lane half, opaque to the compiler here: the 32 row offsets of the
+        const bool may_self = __ballot(qid_l >= col0 && qid_l < col0 + kSkCols) != 0;
+        // the lane half, opaque to the compiler here: the row offsets of the
         // epilogue are then computed in place, not hoisted out of the row-block
-        // loop (where they would hold 32 registers through the MFMAs)
+        // loop (where they would hold registers through the MFMAs)
         uint32_t hv = h;
         asm volatile("" : "+v"(hv));
         // Instantiated for blocks wholly inside the matrix (no row or column
@@ -203,60 +175,58 @@ __global__ __launch_bounds__(kSkThreads) void dist_gemm_sk_kernel(DistArgs a, ui
         // scalar masks.
         auto epilogue = [&](auto edge_t, auto self_t) {
             constexpr bool EDGE = decltype(edge_t)::value, SELF = decltype(self_t)::value;
+            float taus[16];
 #pragma unroll
-            for (int bi = 0; bi < 2; ++bi) {
-                // the 16 thresholds of this row block half, fetched together
-                float taus[16];
+            for (int r = 0; r < 16; ++r) taus[r] = __shfl(tau_l, 8 * (r / 4) + 4 * (int)hv + (r % 4));
 #pragma unroll
-                for (int r = 0; r < 16; ++r) taus[r] = __shfl(tau_l, bi * 32 + 8 * (r / 4) + 4 * (int)hv + (r % 4));
+            for (int r = 0; r < 16; ++r) {
+                const int rl = 8 * (r / 4) + 4 * (int)hv + (r % 4);
+                const int64_t gi = rb * 32 + rl;
+                const float tau = taus[r];
+                const float qs = PREC == kPrecFP8 ? __shfl(qs_l, rl) : 1.f;
+                int64_t qid = -1;
+                if (SELF) qid = (int64_t)__shfl((long long)qid_l, rl);
+                const bool row_ok = !EDGE || gi < a.m;
+                float dp[NB];
+                uint64_t m[NB];
+                uint64_t any = 0;
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int rl = bi * 32 + 8 * (r / 4) + 4 * (int)hv + (r % 4);
-                    const int64_t gi = rb * 64 + rl;
-                    const float tau = taus[r];
-                    const float qs = PREC == kPrecFP8 ? __shfl(qs_l, rl) : 1.f;
-                    int64_t qid = -1;
-                    if (SELF) qid = (int64_t)__shfl((long long)qid_l, rl);
-                    const bool row_ok = !EDGE || gi < a.m;
-                    float dp[4];
-                    uint64_t m[4];
+                for (int bj = 0; bj < NB; ++bj) {
+                    const float dot = PREC == kPrecFP8 ? acc[bj][r] * qs : acc[bj][r];
+                    dp[bj] = fmaf(cs[bj], dot, cn[bj]);
+                    bool pass = dp[bj] <= tau;
+                    const uint32_t gj = gj0 + 32 * bj;
+                    if (EDGE) pass = pass & row_ok & ((int64_t)gj < a.n);
+                    if (SELF) pass = pass & ((int64_t)gj != qid);
+                    m[bj] = __ballot(pass);
+                    any |= m[bj];
+                }
+                // most accumulator rows keep nothing: one test for all eight
+                if (any == 0) {
+                    __builtin_amdgcn_sched_barrier(0);
+                    continue;
+                }
 #pragma unroll
-                    for (int bj = 0; bj < 4; ++bj) {
-                        const float dot = PREC == kPrecFP8 ? acc[bi][bj][r] * qs : acc[bi][bj][r];
-                        dp[bj] = fmaf(cs[bj], dot, cn[bj]);
-                        bool pass = dp[bj] <= tau;
-                        if (EDGE) pass = pass & row_ok & ((int64_t)gj[bj] < a.n);
-                        if (SELF) pass = pass & ((int64_t)gj[bj] != qid);
-                        m[bj] = __ballot(pass);
-                    }
-                    // most accumulator rows keep nothing: one test for all four
-                    if ((m[0] | m[1] | m[2] | m[3]) == 0) {
-                        __builtin_amdgcn_sched_barrier(0);
-                        continue;
-                    }
-#pragma unroll
-                    for (int bj = 0; bj < 4; ++bj) {
-                        if (m[bj]) {
-                            const bool mine = (m[bj] >> lane) & 1ull;
-                            const uint32_t hm = h ? (uint32_t)(m[bj] >> 32) : (uint32_t)m[bj];
-                            uint32_t v = 0;
-                            if (l32 == 0 && hm) v = atomicAdd(&a.cnt[gi], (uint32_t)__popc(hm));
-                            const uint32_t b0 = __shfl(v, 0), b1 = __shfl(v, 32);
-                            if (mine) {
-                                const uint32_t below =
-                                    lanes_below(m[bj]) - (h ? (uint32_t)__popc((uint32_t)m[bj]) : 0u);
-                                const uint32_t slot = (h ? b1 : b0) + below;
-                                if (slot < (uint32_t)a.cap) a.cand[gi * a.cap + slot] = make_key(dp[bj], gj[bj]);
-                            }
+                for (int bj = 0; bj < NB; ++bj) {
+                    if (m[bj]) {
+                        const bool mine = (m[bj] >> lane) & 1ull;
+                        const uint32_t hm = h ? (uint32_t)(m[bj] >> 32) : (uint32_t)m[bj];
+                        uint32_t v = 0;
+                        if (l32 == 0 && hm) v = atomicAdd(&a.cnt[gi], (uint32_t)__popc(hm));
+                        const uint32_t b0 = __shfl(v, 0), b1 = __shfl(v, 32);
+                        if (mine) {
+                            const uint32_t below = lanes_below(m[bj]) - (h ? (uint32_t)__popc((uint32_t)m[bj]) : 0u);
+                            const uint32_t slot = (h ? b1 : b0) + below;
+                            if (slot < (uint32_t)a.cap) a.cand[gi * a.cap + slot] = make_key(dp[bj], gj0 + 32 * bj);
                         }
                     }
-                    // one accumulator row at a time (hoisting the others' work
-                    // would hold them all in registers)
-                    __builtin_amdgcn_sched_barrier(0);
                 }
+                // one accumulator row at a time (hoisting the others' work
+                // would hold them all in registers)
+                __builtin_amdgcn_sched_barrier(0);
             }
         };
-        const bool edge = rb * 64 + 64 > a.m || cw0 + 128 > a.n;
+        const bool edge = rb * 32 + 32 > a.m || col0 + kSkCols > a.n;
         if (edge) {
             if (may_self) epilogue(std::true_type{}, std::true_type{});
             else epilogue(std::true_type{}, std::false_type{});
