@@ -91,12 +91,13 @@ int size_bucket(int64_t x) {
 }
 
 hipError_t autotune_pick(const std::string &key, const std::vector<int> &candidates,
-                         const std::function<hipError_t(int)> &run, hipStream_t stream, int reps, int *choice) {
+                         const std::function<hipError_t(int)> &run, hipStream_t stream, int reps, int *choice,
+                         float margin) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
     int best = candidates.empty() ? -1 : candidates[0];
-    float best_ms = 0.f;
+    float best_ms = 0.f, first_ms = 0.f;
     for (size_t ci = 0; e == hipSuccess && ci < candidates.size(); ++ci) {
         const int c = candidates[ci];
         e = run(c);  // warm-up
@@ -110,11 +111,13 @@ hipError_t autotune_pick(const std::string &key, const std::vector<int> &candida
             if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
             if (e == hipSuccess && (r == 0 || ms < cand_ms)) cand_ms = ms;
         }
+        if (e == hipSuccess && ci == 0) first_ms = cand_ms;
         if (e == hipSuccess && (ci == 0 || cand_ms < best_ms)) {
             best_ms = cand_ms;
             best = c;
         }
     }
+    if (!candidates.empty() && best != candidates[0] && best_ms > first_ms * (1.f - margin)) best = candidates[0];
     if (e0) hipEventDestroy(e0);
     if (e1) hipEventDestroy(e1);
     if (e != hipSuccess) return e;

@@ -26,9 +26,12 @@ int autotune_lookup(const std::string &key);
 
 // Times run(c) for every candidate c on `stream` (one warm-up launch, then the
 // best of `reps` timed launches) and returns the fastest in *choice, recording
-// it under `key`.  The stream is synchronised.
+// it under `key`; the first candidate (the preferred one) is kept unless
+// another is faster by more than the fraction `margin`.  The stream is
+// synchronised.
 hipError_t autotune_pick(const std::string &key, const std::vector<int> &candidates,
-                         const std::function<hipError_t(int)> &run, hipStream_t stream, int reps, int *choice);
+                         const std::function<hipError_t(int)> &run, hipStream_t stream, int reps, int *choice,
+                         float margin = 0.f);
 
 // log2 bucket of a positive size (floor).
 int size_bucket(int64_t x);
