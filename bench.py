@@ -763,7 +763,7 @@ def bench_lowprec(args, knn, torch, np, synth):
         "roofline": {"bound": "mfma", "kernel": "dist_gemm_sk_kernel (resident corpus, fused filter epilogue, BF16)",
                      "achieved": achieved, "peak": PEAK_MFMA_TFLOPS["bf16"], "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_MFMA_TFLOPS["bf16"], 4),
-                     "traffic": measured_traffic("lowprec_2p20x256_k64_traffic.md", ("gemm_sk.hip",))
+                     "traffic": measured_traffic("lowprec_2p20x256_k64_traffic.md", ("gemm_sk.hip", "plan.hpp"))
                      if precs[0] == "bf16" else None,
                      "launch_ms": res["product_ms_per_launch"],
                      "flops_per_launch": tot["product_flops"] / max(tot["product_launches"], 1)},

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 #include <cstdint>
 
 #include "dist.hpp"
@@ -243,6 +244,31 @@ inline Plan make_plan(int64_t m, int64_t n, int d, int k, bool graph, const knn_
             const bool enough = S * p.kk >= 2 * n && 2.0 * expected <= kSelectKeysCap;
             if (enough || S >= kSampleColsMax || S >= n) break;
             S *= 2;
+        }
+        // then more sample columns while they cost less than the candidates
+        // they save: with a small expected sample rank the margin above it lets
+        // several kk through.  A kept candidate (its slot reservation and key
+        // write in the product, its share of the candidate selection) costs
+        // about 0.19 ns of the device (measured on the 2^20 x 256 BF16 graph);
+        // a sample column costs, per row, its share of the sample product
+        // (2 d flops) and a written and re-read distance.  Short reduced-
+        // precision rows gain (2^20 x 256 BF16, kk = 256: 8192 -> 16384
+        // columns, 1536 -> 960 candidates per row); long FP32 rows keep theirs.
+        {
+            const double t_keep = 1.9e-10;
+            const double t_col = 2.0 * d / (p.prec == kPrecF32 ? 1.25e14 : 6.0e14) + 2.0e-12;
+            while (2 * S <= kSampleColsMax && 2 * S < n) {
+                double e2 = 0;
+                rank_for(2 * S, e2);
+                if (2.0 * e2 > kSelectKeysCap) break;
+                if ((expected - e2) * t_keep <= (double)S * t_col) break;
+                S *= 2;
+                expected = e2;
+            }
+        }
+        if (const char *e = std::getenv("KNN_SAMPLE_COLS")) {
+            const long v = std::atol(e);
+            if (v >= 64 && v <= 65536) S = v;
         }
         p.S = n < S ? (int)n : (int)S;
         p.gathered = n > p.S;
