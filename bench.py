@@ -760,7 +760,8 @@ def bench_lowprec(args, knn, torch, np, synth):
                    "N": N, "d": d, "k": k, "oversample": 4},
         precs[0]: res,
         **others,
-        "roofline": {"bound": "mfma", "kernel": "dist_gemm_sk_kernel (resident corpus, fused filter epilogue, BF16)",
+        "roofline": {"bound": "mfma", "kernel": "dist_gemm_sk_kernel + sk_append_kernel (resident corpus, fused filter"
+                                                   " epilogue with the kept keys staged per wave, BF16)",
                      "achieved": achieved, "peak": PEAK_MFMA_TFLOPS["bf16"], "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_MFMA_TFLOPS["bf16"], 4),
                      "traffic": measured_traffic("lowprec_2p20x256_k64_traffic.md", ("gemm_sk.hip", "plan.hpp"))

@@ -45,6 +45,12 @@ struct DistArgs {
     const float *cscale;
     // tile shape (kTile*), or -1 for the default choice of gemm_tile_choice
     int tile = -1;
+    // FILTER with the resident-corpus product only (optional): stage_bytes of
+    // device memory where each wave appends its kept keys without atomics; a
+    // second pass then appends them to the rows (cnt / cand as above).  Null:
+    // every kept key is appended to its row in the product itself.
+    void *stage = nullptr;
+    int64_t stage_bytes = 0;
     // filled by the launcher
     uint32_t tiles_m, tiles_n;
 };

@@ -77,6 +77,8 @@ struct Bufs {
     float *tfix = nullptr;
     void *selws = nullptr;
     float *ninf = nullptr;  // one -inf: threshold of the tile-timing launches
+    void *stage = nullptr;  // kept-key staging of the resident-corpus product
+    size_t stage_bytes = 0;
 };
 
 inline size_t carve(Carve &c, const Plan &p, Bufs &b, int num_cu) {
@@ -120,6 +122,14 @@ inline size_t carve(Carve &c, const Plan &p, Bufs &b, int num_cu) {
         b.ti = c.take<int32_t>((size_t)p.Mb * (p.r + 1));
         b.cnt = c.take<uint32_t>(p.Mb);
         b.cand = c.take<uint64_t>((size_t)p.Mb * p.cap);
+        if (p.prec != kPrecF32 && p.ldq <= 512) {
+            // room for every row's full candidate list (key and row), plus one
+            // count per wave of the resident-corpus grid (at most 8 waves per
+            // 256 columns per 512 rows)
+            const size_t waves = (size_t)((p.n + 255) / 256) * (size_t)(p.Mb / 512 + 2) * 8;
+            b.stage_bytes = (size_t)p.Mb * p.cap * 12 + waves * 4 + 256;
+            b.stage = c.take<char>(b.stage_bytes);
+        }
         b.flags = c.take<int32_t>(p.Mb);
         b.nflag = c.take<uint32_t>(1);
         b.sv = c.take<float>((size_t)p.Mb * p.kk);

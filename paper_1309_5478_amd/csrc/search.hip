@@ -322,6 +322,8 @@ knn_status_t run_search(knn_handle_t h, const float *Q, int64_t m, const float *
         fa.cand = b.cand;
         fa.cap = p.cap;
         fa.tile = ftile;
+        fa.stage = b.stage;
+        fa.stage_bytes = (int64_t)b.stage_bytes;
         set_prec(fa, qrow(i0), qsrow(i0), Cq, csc);
         KNN_TRY(timer.begin(stream, 2.0 * (double)mb * (double)n * d));
         KNN_TRY(launch_dist_gemm(fa, kEpiFilter, stream));

@@ -70,3 +70,27 @@ def test_sk_lattice_exact(h, torch):
     gd, gi = run(h, torch, None, P, 20, "bf16", True, graph=True)
     rows = np.arange(0, 6000, 97)
     compare(P, P, 20, gd[rows], gi[rows], rows, self_ids=np.arange(6000))
+
+
+@pytest.mark.parametrize("prec,d", [("bf16", 256), ("fp8", 200)])
+@pytest.mark.parametrize("stage", ["0", "64"])
+def test_sk_staging_forms(h, torch, prec, d, stage):
+    """The kept keys staged per wave (the default), appended to the rows in the
+    product itself (KNN_SK_STAGE=0), and staged with room for only 64 keys per
+    wave, so that most go to the rows directly once a wave's part is full: the
+    same candidate sets, so the same bits."""
+    n = 20000 + 17
+    C = synth.gmm_points(n, d, seed=90 + d)
+    Q = synth.gmm_points(2000 + 3, d, seed=91 + d)
+    for graph in (False, True):
+        for k in (16, 300):
+            say(f"sk staging {stage}: {prec} d={d} graph={graph} k={k}")
+            a = run(h, torch, Q, C, k, prec, True, graph)
+            var = "KNN_SK_STAGE" if stage == "0" else "KNN_SK_STAGE_KEYS"
+            os.environ[var] = stage
+            try:
+                b = run(h, torch, Q, C, k, prec, True, graph)
+            finally:
+                del os.environ[var]
+            assert np.array_equal(a[1], b[1])
+            assert np.array_equal(a[0].view(np.uint32), b[0].view(np.uint32))
