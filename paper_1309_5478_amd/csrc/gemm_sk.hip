@@ -160,7 +160,11 @@ __global__ __launch_bounds__(kSkThreads) void dist_gemm_sk_kernel(DistArgs a, ui
     for (; rb < rb1; rb += kSkWaves) {
         const int64_t nxt = rb + kSkWaves;
         const bool more = nxt < rb1;
+        // the accumulators start from zero (set here, not chosen per k-step:
+        // in a rolled loop that choice is a select per accumulator element)
         f32x16 acc[NB];
+#pragma unroll
+        for (int bj = 0; bj < NB; ++bj) acc[bj] = zero;
         // each corpus fragment is read from LDS where it is used; BF16 takes
         // the k-steps unrolled, FP8 (fragments twice the size) one at a time,
         // so that the eight accumulator blocks and the rest fit 256 registers
@@ -169,7 +173,7 @@ __global__ __launch_bounds__(kSkThreads) void dist_gemm_sk_kernel(DistArgs a, ui
 #pragma unroll
             for (int bj = 0; bj < NB; ++bj) {
                 const F b = bfrag(s, bj);
-                acc[bj] = mfma<PREC>(ring[s % P], b, s == 0 ? zero : acc[bj]);
+                acc[bj] = mfma<PREC>(ring[s % P], b, acc[bj]);
             }
             // refill the slot just read: this block's step s + P, or the next block's
             if (s + P < S) ring[s % P] = qfrag(rb, s + P);
