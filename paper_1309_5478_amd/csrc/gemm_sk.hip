@@ -286,12 +286,26 @@ __global__ __launch_bounds__(256) void sk_append_kernel(SkStage st, uint64_t nwa
     const uint64_t w = (uint64_t)blockIdx.x * 4 + threadIdx.x / kWave;
     if (w >= nwaves) return;
     const uint32_t n = st.cnt[w], lane = threadIdx.x % kWave;
-    const uint32_t *srow = st.row + w * st.wcap;
-    const uint64_t *skey = st.key + w * st.wcap;
-    for (uint32_t i = lane; i < n; i += kWave) {
-        const uint32_t row = srow[i];
-        const uint32_t slot = atomicAdd(&cnt[row], 1u);
-        if (slot < (uint32_t)cap) cand[(size_t)row * cap + slot] = skey[i];
+    const uint32_t *__restrict__ srow = st.row + w * st.wcap;
+    const uint64_t *__restrict__ skey = st.key + w * st.wcap;
+    // two keys per lane at a time, each key loaded with its row, so that both
+    // slot reservations are in flight together
+    for (uint32_t i = lane; i < n; i += 2 * kWave) {
+        const uint32_t j = i + kWave;
+        const bool two = j < n;
+        const uint32_t r0 = srow[i];
+        const uint64_t k0 = skey[i];
+        uint32_t r1 = 0;
+        uint64_t k1 = 0;
+        if (two) {
+            r1 = srow[j];
+            k1 = skey[j];
+        }
+        const uint32_t s0 = atomicAdd(&cnt[r0], 1u);
+        uint32_t s1 = 0xffffffffu;
+        if (two) s1 = atomicAdd(&cnt[r1], 1u);
+        if (s0 < (uint32_t)cap) cand[(size_t)r0 * cap + s0] = k0;
+        if (s1 < (uint32_t)cap) cand[(size_t)r1 * cap + s1] = k1;
     }
 }
 
