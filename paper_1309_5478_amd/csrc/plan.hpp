@@ -263,7 +263,8 @@ inline Plan make_plan(int64_t m, int64_t n, int d, int k, bool graph, const knn_
         // a sample column costs, per row, its share of the sample product
         // (2 d flops) and a written and re-read distance.  Short reduced-
         // precision rows gain (2^20 x 256 BF16, kk = 256: 8192 -> 16384
-        // columns, 1536 -> 960 candidates per row); long FP32 rows keep theirs.
+        // columns, 1536 -> 1024 candidates per row expected, 1544 -> 1038
+        // measured); long FP32 rows keep theirs.
         {
             const double t_keep = 1.9e-10;
             const double t_col = 2.0 * d / (p.prec == kPrecF32 ? 1.25e14 : 6.0e14) + 2.0e-12;
